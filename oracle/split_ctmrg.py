@@ -1,0 +1,562 @@
+"""Plain FP64 CPU split-CTMRG (test oracle; not part of the product path).
+
+Follows Sec. II B of the paper (split environment of Fig. split-transfer-ctmrg,
+left move of Eqs. splitCTMRG_C1, splitCTMRG_C4, splitCTMRG_Tket,
+splitCTMRG_Tbra), the projector recipe of Fig. proj_plots_green and the
+projector constructions of App. A.  Written with torch float64 CPU tensors so
+that autograd gives an independent gradient.  Only real PEPS tensors are
+supported (bra = ket).
+
+Leg conventions are those of paper_2502_10298_amd.inputs (ring order, first /
+second split transfer tensor along each edge).
+
+Readings of the paper (it is silent or its figures are missing):
+  * teal / red half networks (their figure bodies are missing): the
+    intermediate environment after the ket half-step, i.e. the 1-column patch
+    with the green and yellow projectors already inserted (App. A says the
+    teal/red networks contain the green/yellow projectors).  Parity unpinned
+    against the paper itself; pinned indirectly (Ising, product states,
+    convergence to the conventional CTMRG).
+  * singular values below cutoff * s_1 are dropped (cutoff 1e-12);
+  * canonical sign: the entry of largest magnitude of every column of P_T is
+    made positive (lowest index on ties), flipping the matching column of P_B;
+  * the unit cell is treated column by column, every site carrying its own
+    environment; top/right/bottom moves are the left move in a transposed,
+    rotated or anti-transposed frame (Sec. II B only says "analogous");
+  * every new C / T is divided by its Frobenius norm;
+  * one sweep = left, top, right, bottom move; convergence measure = largest
+    2-norm change of the singular values of any corner.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Tuple
+
+import torch
+
+from .svd_adjoint import svd as broadened_svd
+
+DT = torch.float64
+NAMES = ("C1", "C2", "C3", "C4", "T1k", "T1b", "T2k", "T2b", "T3b", "T3k", "T4b", "T4k")
+
+
+# ----------------------------------------------------------------------------
+# A small greedy pairwise einsum (torch.einsum contracts left to right, which
+# builds huge intermediates for ten-tensor networks).
+# ----------------------------------------------------------------------------
+def ncon(spec: str, *ops: torch.Tensor) -> torch.Tensor:
+    lhs, out = spec.split("->")
+    terms = lhs.split(",")
+    assert len(terms) == len(ops), spec
+    dims = {}
+    for t, o in zip(terms, ops):
+        assert len(t) == o.dim(), (spec, t, tuple(o.shape))
+        for c, n in zip(t, o.shape):
+            assert dims.setdefault(c, n) == n, (spec, c)
+    items = list(zip(terms, ops))
+    while len(items) > 1:
+        best = None
+        for i in range(len(items)):
+            for j in range(i + 1, len(items)):
+                ti, tj = items[i][0], items[j][0]
+                rest = set(out)
+                for k, (tk, _) in enumerate(items):
+                    if k != i and k != j:
+                        rest |= set(tk)
+                union = list(dict.fromkeys(ti + tj))
+                keep = "".join(c for c in union if c in rest)
+                shared = bool(set(ti) & set(tj))
+                flops = math.prod(dims[c] for c in union)
+                size = math.prod(dims[c] for c in keep)
+                key = (not shared, flops, size)
+                if best is None or key < best[0]:
+                    best = (key, i, j, keep)
+        _, i, j, keep = best
+        (ti, Ti), (tj, Tj) = items[i], items[j]
+        new = torch.einsum(f"{ti},{tj}->{keep}", Ti, Tj)
+        items = [it for k, it in enumerate(items) if k not in (i, j)] + [(keep, new)]
+    t, T = items[0]
+    return torch.einsum(f"{t}->{out}", T)
+
+
+# ----------------------------------------------------------------------------
+# Projector recipe (Fig. proj_plots_green (b), (c); Sec. II B text)
+# ----------------------------------------------------------------------------
+class RankZero(RuntimeError):
+    pass
+
+
+def projectors(rhoT: torch.Tensor, rhoB: torch.Tensor, n_a: int, chi: int,
+               cutoff: float = 1e-12, adj_eps: float = 1e-12):
+    """Projector pair from the two half networks.
+
+    rhoT / rhoB: upper / lower half of a closed patch; their first n_a legs are
+    the legs to truncate (a), the remaining legs (b) stay open.
+      M[bB, bT] = sum_a rhoB[a, bB] rhoT[a, bT] = U S V^T
+      P_T[a, k] = s_k^{-1/2} sum_bB U[bB, k] rhoB[a, bB]   (placed above the cut)
+      P_B[a, k] = s_k^{-1/2} sum_bT V[bT, k] rhoT[a, bT]   (placed below the cut)
+    so that rhoB P_B P_T rhoT is the rank-k truncation of M (the approximate
+    resolution of the identity built from M's truncated SVD).
+    Returns (P_T, P_B, S_full, k) with P of shape a_shape + (k,)."""
+    a_shape = tuple(rhoT.shape[:n_a])
+    assert tuple(rhoB.shape[:n_a]) == a_shape
+    na = math.prod(a_shape)
+    RT = rhoT.reshape(na, -1)
+    RB = rhoB.reshape(na, -1)
+    M = RB.T @ RT
+    U, S, V = broadened_svd(M, adj_eps)
+    s1 = float(S[0]) if S.numel() else 0.0
+    if not (s1 > 0.0) or not math.isfinite(s1):
+        raise RankZero("projector matrix has rank zero or is not finite")
+    k = min(chi, int((S > cutoff * s1).sum()))
+    isq = S[:k].rsqrt()
+    PT = (RB @ U[:, :k]) * isq[None, :]
+    PB = (RT @ V[:, :k]) * isq[None, :]
+    PT, PB = _sign_fix(PT, PB)
+    return PT.reshape(*a_shape, k), PB.reshape(*a_shape, k), S.detach(), k
+
+
+def projectors_qr(rhoT: torch.Tensor, rhoB: torch.Tensor, n_a: int, chi: int,
+                  cutoff: float = 1e-12):
+    """Same projectors through a pre-decomposition of each half network
+    (App. A, yellow projectors: decompose rhoT and rhoB before multiplying them,
+    since their rank is at most dim(a)).  rho^T = Q R (Householder, R diagonal
+    >= 0); core K = R_B R_T^T = X Sigma Y^T; P_T = R_B^T X Sigma^{-1/2},
+    P_B = R_T^T Y Sigma^{-1/2}.  Identical to `projectors` up to rounding."""
+    a_shape = tuple(rhoT.shape[:n_a])
+    na = math.prod(a_shape)
+    RT = rhoT.reshape(na, -1)
+    RB = rhoB.reshape(na, -1)
+    assert RT.shape[1] >= na, "QR form needs dim b >= dim a"
+
+    def rfac(X):
+        R = torch.linalg.qr(X.T, mode="r")[1]
+        sgn = torch.where(torch.diagonal(R) < 0, -1.0, 1.0).to(DT)
+        return sgn[:, None] * R
+
+    R_T, R_B = rfac(RT), rfac(RB)
+    K = R_B @ R_T.T
+    X, Sg, Yh = torch.linalg.svd(K)
+    s1 = float(Sg[0])
+    if not (s1 > 0.0):
+        raise RankZero("projector core has rank zero")
+    k = min(chi, int((Sg > cutoff * s1).sum()))
+    isq = Sg[:k].rsqrt()
+    PT = (R_B.T @ X[:, :k]) * isq[None, :]
+    PB = (R_T.T @ Yh[:k].T) * isq[None, :]
+    PT, PB = _sign_fix(PT, PB)
+    return PT.reshape(*a_shape, k), PB.reshape(*a_shape, k), Sg, k
+
+
+def _sign_fix(PT: torch.Tensor, PB: torch.Tensor):
+    """Make the largest-magnitude entry of every column of P_T positive."""
+    with torch.no_grad():
+        idx = PT.abs().argmax(dim=0)           # first maximum on ties
+        sg = torch.sign(PT[idx, torch.arange(PT.shape[1])])
+        sg = torch.where(sg == 0, torch.ones_like(sg), sg)
+    return PT * sg[None, :], PB * sg[None, :]
+
+
+# ----------------------------------------------------------------------------
+# Half networks of one site (left move).  e = environment of the site, A its
+# PEPS tensor; the bra tensor is A itself (real states).
+# ----------------------------------------------------------------------------
+def rho_green_top(e, A):
+    """Upper half of the 2-row, 1-column patch, Fig. proj_plots_green (a):
+    open legs (E = T4b.d, K = ket.d | B = bra.d, F = T2b.d)."""
+    return ncon("ab,bce,efg,gh,hij,jkF,xya,Ewx,zcyKi,zfwBk->EKBF",
+                e["C1"], e["T1k"], e["T1b"], e["C2"], e["T2k"], e["T2b"],
+                e["T4k"], e["T4b"], A, A)
+
+
+def rho_green_bottom(e, A):
+    """Lower half of the patch: open legs (E = T4k.u, K = ket.u | B = bra.u, F = T2k.u)."""
+    return ncon("xyE,vwx,tv,qrt,noq,mn,jkm,Fij,zKyri,zBwok->EKBF",
+                e["T4k"], e["T4b"], e["C4"], e["T3k"], e["T3b"], e["C3"],
+                e["T2b"], e["T2k"], A, A)
+
+
+def rho_yellow_top(e, A):
+    """Fig. constructionYellowProjectors, rho^T: the ket sub-row with the top
+    edge; open legs (I = T4k.d, K = ket.d | P = ket phys, W = T1b.s, J = T2k.d)."""
+    return ncon("ab,bce,eWg,gh,hiJ,Iya,PcyKi->IKPWJ",
+                e["C1"], e["T1k"], e["T1b"], e["C2"], e["T2k"], e["T4k"], A)
+
+
+def rho_yellow_bottom(e, A):
+    """rho^B: the bra sub-row with the bottom edge; open legs
+    (I = T4b.u, K = T3k.s | P = bra phys, W = bra.u, J = T2b.u)."""
+    return ncon("vwI,tv,qKt,noq,mn,Jkm,PWwok->IKPWJ",
+                e["T4b"], e["C4"], e["T3k"], e["T3b"], e["C3"], e["T2b"], A)
+
+
+# ----------------------------------------------------------------------------
+# One left move (Eqs. splitCTMRG_C1/C4/Tket/Tbra, App. A)
+# ----------------------------------------------------------------------------
+def _normalize(t):
+    return t / torch.linalg.norm(t)
+
+
+def _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps):
+    """Green and yellow projectors of column y (left side, ket layer first) and
+    the mirrored pair of the same column for its right side (bra layer first).
+
+    The half networks are those of Fig. proj_plots_green (a) and
+    Fig. constructionYellowProjectors.  Left side: green truncates (E, K) on
+    the cut (x|x+1), yellow truncates (I, K) on the ket|bra cut of row x.
+    Right side (the same half networks split the other way): green' truncates
+    (B, F), yellow' truncates (W, J)."""
+    G, Y, Gr, Yr = {}, {}, {}, {}
+    for x in range(Lx):
+        xp = (x + 1) % Lx
+        gT = rho_green_top(env[(x, y)], A[(x, y)])
+        gB = rho_green_bottom(env[(xp, y)], A[(xp, y)])
+        G[x] = projectors(gT, gB, 2, chi_E, cutoff, adj_eps)
+        Gr[x] = projectors(gT.permute(2, 3, 0, 1), gB.permute(2, 3, 0, 1), 2, chi_E, cutoff, adj_eps)
+        yT = rho_yellow_top(env[(x, y)], A[(x, y)])
+        yB = rho_yellow_bottom(env[(x, y)], A[(x, y)])
+        Y[x] = projectors(yT, yB, 2, chi_I, cutoff, adj_eps)
+        Yr[x] = projectors(yT.permute(3, 4, 0, 1, 2), yB.permute(3, 4, 0, 1, 2), 2, chi_I,
+                           cutoff, adj_eps)
+    return G, Y, Gr, Yr
+
+
+def left_intermediate(env, A, Lx, y, G, Y):
+    """Ket half-step of column y: absorb the ket layer into the left
+    environment and apply the first (green, yellow) projectors.
+    C1t[g,e], T4kt[g,S,Y,P] (P = open physical leg), T4bt[Y,w,g], C4t[g,q]."""
+    C1t, T4kt, T4bt, C4t = {}, {}, {}, {}
+    for x in range(Lx):
+        e, a = env[(x, y)], A[(x, y)]
+        GT_up, GB_up = G[(x - 1) % Lx][0], G[(x - 1) % Lx][1]
+        GT_dn, GB_dn = G[x][0], G[x][1]
+        YT, YB = Y[x][0], Y[x][1]
+        C1t[x] = ncon("ab,bce,acg->ge", e["C1"], e["T1k"], GT_up)
+        T4kt[x] = ncon("xya,PcykS,acg,xkY->gSYP", e["T4k"], a, GB_up, YT)
+        T4bt[x] = ncon("vwx,xkY,vkg->Ywg", e["T4b"], YB, GT_dn)
+        C4t[x] = ncon("tv,qrt,vrg->gq", e["C4"], e["T3k"], GB_dn)
+    return C1t, T4kt, T4bt, C4t
+
+
+def right_intermediate(env, A, Lx, y, Gr, Yr):
+    """Bra half-step of the right environment of column y (mirror image of
+    left_intermediate: the bra layer sits next to C2 and C3 on the top and
+    bottom edges).  C2t[e,k] (left chi_I, down), T2kt[k,S,i] (up, ket.r, down),
+    T2bt[i,w,k,P] (up, bra.l, down, open physical leg), C3t[k,i] (up, left)."""
+    C2t, T2kt, T2bt, C3t = {}, {}, {}, {}
+    for x in range(Lx):
+        e, a = env[(x, y)], A[(x, y)]
+        GT_up, GB_up = Gr[(x - 1) % Lx][0], Gr[(x - 1) % Lx][1]
+        GT_dn, GB_dn = Gr[x][0], Gr[x][1]
+        YT, YB = Yr[x][0], Yr[x][1]
+        C2t[x] = ncon("gF,eBg,BFk->ek", e["C2"], e["T1b"], GT_up)
+        T2kt[x] = ncon("FSJ,WFk,WJi->kSi", e["T2k"], GB_up, YT)
+        T2bt[x] = ncon("JkF,PWwBk,WJi,BFg->iwgP", e["T2b"], a, YB, GT_dn)
+        C3t[x] = ncon("Fq,qBi,BFk->ki", e["C3"], e["T3b"], GB_dn)
+    return C2t, T2kt, T2bt, C3t
+
+
+def left_move(env: Dict, A: Dict, Lx: int, Ly: int, chi_E: int, chi_I: int,
+              cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None):
+    """Absorb every column of the cell into the left environment, in place.
+
+    Column y, every row x:
+      1. green / yellow projectors of column y (ket layer) and the mirrored
+         pair of column y+1 (bra layer of the right environment);
+      2. ket half-step: intermediate left environment of column y, and the
+         intermediate right environment of column y+1;
+      3. teal projectors on the cut (x|x+1) and red projectors on the ket|bra
+         cut of row x, from the 2-column patch
+            [left env after ket step][bra of column y][ket of column y+1][right env after bra step]
+         (App. A: these half networks contain the first projectors; the b
+         legs are (D, chi_E) for teal and (D, p, chi_I) for red);
+      4. bra half-step: new C1, T4k, T4b, C4 of site [x, y+1], normalised."""
+    for y in range(Ly):
+        yn = (y + 1) % Ly
+        G, Y, Gr, Yr = _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps)
+        if yn != y:
+            Gr, Yr = _first_projectors(env, A, Lx, yn, chi_E, chi_I, cutoff, adj_eps)[2:]
+        C1t, T4kt, T4bt, C4t = left_intermediate(env, A, Lx, y, G, Y)
+        C2t, T2kt, T2bt, C3t = right_intermediate(env, A, Lx, yn, Gr, Yr)
+        TH, R = {}, {}
+        for x in range(Lx):
+            xp = (x + 1) % Lx
+            m, mp = env[(x, y)], env[(xp, y)]          # middle: bra part of column y
+            n, np_ = env[(x, yn)], env[(xp, yn)]       # middle: ket part of column y+1
+            b, bp = A[(x, y)], A[(xp, y)]
+            k, kp = A[(x, yn)], A[(xp, yn)]
+            rT = ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
+                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
+                      T2kt[x], T2bt[x])
+            rB = ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
+                      T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
+                      T2kt[xp], T2bt[xp])
+            TH[x] = projectors(rT, rB, 2, chi_E, cutoff, adj_eps)
+            sT = ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
+                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
+            sB = ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
+                      T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
+            R[x] = projectors(sT, sB, 3, chi_I, cutoff, adj_eps)
+        new = {}
+        for x in range(Lx):
+            e, a = env[(x, y)], A[(x, y)]
+            ThT_up, ThB_up = TH[(x - 1) % Lx][0], TH[(x - 1) % Lx][1]
+            ThT_dn, ThB_dn = TH[x][0], TH[x][1]
+            RT, RB = R[x][0], R[x][1]
+            new[x] = dict(
+                C1=_normalize(ncon("ge,efR,gfD->DR", C1t[x], e["T1b"], ThT_up)),
+                T4k=_normalize(ncon("gSYP,gWU,YPWD->DSU", T4kt[x], ThB_up, RT)),
+                T4b=_normalize(ncon("Ywg,PWwBs,YPWU,gBD->DsU", T4bt[x], a, RB, ThT_dn)),
+                C4=_normalize(ncon("gq,Roq,goU->RU", C4t[x], e["T3b"], ThB_dn)),
+            )
+        if info is not None:
+            for x in range(Lx):
+                for tag, pr in (("green", G[x]), ("yellow", Y[x]), ("teal", TH[x]), ("red", R[x])):
+                    S = pr[2]
+                    tot = float((S * S).sum())
+                    kept = float((S[: pr[3]] ** 2).sum())
+                    info.setdefault("trunc_err", []).append((tag, (tot - kept) / tot if tot > 0 else 0.0))
+                    info.setdefault("k", []).append((tag, pr[3]))
+        for x in range(Lx):
+            site = dict(env[(x, yn)])
+            site.update(new[x])
+            env[(x, yn)] = site
+
+
+# ----------------------------------------------------------------------------
+# Lattice symmetries used to run the other moves as left moves
+# ----------------------------------------------------------------------------
+def _rev(t):
+    return t.permute(2, 1, 0)
+
+
+def frame_transpose(env, A, Lx, Ly):
+    """Reflection through the line joining the C1 and C3 corners: rows <->
+    columns, u <-> l, d <-> r.  The ring runs backwards, so C1, C3 are
+    transposed, C2 <-> C4 (transposed), T1 <-> T4 and T2 <-> T3 (each leg
+    order reversed).  The first layer along each edge stays the ket layer on
+    the top/left edges."""
+    env2, A2 = {}, {}
+    for (x, y), e in env.items():
+        env2[(y, x)] = dict(
+            C1=e["C1"].T, C2=e["C4"].T, C3=e["C3"].T, C4=e["C2"].T,
+            T1k=_rev(e["T4k"]), T1b=_rev(e["T4b"]), T4k=_rev(e["T1k"]), T4b=_rev(e["T1b"]),
+            T2k=_rev(e["T3k"]), T2b=_rev(e["T3b"]), T3k=_rev(e["T2k"]), T3b=_rev(e["T2b"]))
+        A2[(y, x)] = A[(x, y)].permute(0, 2, 1, 4, 3)
+    return env2, A2, Ly, Lx
+
+
+def frame_rotate(env, A, Lx, Ly):
+    """Rotation by 180 degrees: C1 <-> C3, C2 <-> C4, T1 <-> T3, T2 <-> T4 with
+    the leg order kept.  The tensor adjacent to the new C1 along the new top
+    edge is the old T3b, so ket and bra layers swap roles (the bra layer is
+    absorbed first in a right or bottom move)."""
+    env2, A2 = {}, {}
+    for (x, y), e in env.items():
+        env2[((-x) % Lx, (-y) % Ly)] = dict(
+            C1=e["C3"], C2=e["C4"], C3=e["C1"], C4=e["C2"],
+            T1k=e["T3b"], T1b=e["T3k"], T2k=e["T4b"], T2b=e["T4k"],
+            T3b=e["T1k"], T3k=e["T1b"], T4b=e["T2k"], T4k=e["T2b"])
+        A2[((-x) % Lx, (-y) % Ly)] = A[(x, y)].permute(0, 3, 4, 1, 2)
+    return env2, A2, Lx, Ly
+
+
+def to_frame(direction: str, env, A, Lx, Ly):
+    if direction == "left":
+        return env, A, Lx, Ly
+    if direction == "top":
+        return frame_transpose(env, A, Lx, Ly)
+    if direction == "right":
+        return frame_rotate(env, A, Lx, Ly)
+    if direction == "bottom":
+        e2, a2, lx, ly = frame_transpose(env, A, Lx, Ly)
+        return frame_rotate(e2, a2, lx, ly)
+    raise ValueError(direction)
+
+
+def from_frame(direction: str, env, A, Lx, Ly):
+    """Inverse of to_frame (each map is an involution; bottom = rotate o transpose)."""
+    if direction == "left":
+        return env, A, Lx, Ly
+    if direction == "top":
+        return frame_transpose(env, A, Lx, Ly)
+    if direction == "right":
+        return frame_rotate(env, A, Lx, Ly)
+    if direction == "bottom":
+        e2, a2, lx, ly = frame_rotate(env, A, Lx, Ly)
+        return frame_transpose(e2, a2, lx, ly)
+    raise ValueError(direction)
+
+
+def move(direction: str, env, A, Lx, Ly, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, info=None):
+    e2, a2, lx, ly = to_frame(direction, env, A, Lx, Ly)
+    left_move(e2, a2, lx, ly, chi_E, chi_I, cutoff, adj_eps, info)
+    e3, _, _, _ = from_frame(direction, e2, a2, lx, ly)
+    return e3
+
+
+# ----------------------------------------------------------------------------
+# Sweeps and convergence
+# ----------------------------------------------------------------------------
+def corner_spectra(env):
+    out = {}
+    for key, e in env.items():
+        for c in ("C1", "C2", "C3", "C4"):
+            out[(key, c)] = torch.linalg.svdvals(e[c].detach())
+    return out
+
+
+def spectra_delta(s_old, s_new) -> float:
+    d = 0.0
+    for k, a in s_new.items():
+        b = s_old.get(k)
+        if b is None:
+            return math.inf
+        n = max(a.numel(), b.numel())
+        aa = torch.zeros(n, dtype=DT)
+        bb = torch.zeros(n, dtype=DT)
+        aa[: a.numel()] = a
+        bb[: b.numel()] = b
+        d = max(d, float(torch.linalg.norm(aa - bb)))
+    return d
+
+
+def sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, info=None):
+    """One directional split-CTMRG step: left, top, right and bottom moves."""
+    for direction in ("left", "top", "right", "bottom"):
+        env = move(direction, env, A, Lx, Ly, chi_E, chi_I, cutoff, adj_eps, info)
+    return env
+
+
+def run(env, A, Lx, Ly, chi_E, chi_I, max_sweeps, tol=0.0, cutoff=1e-12):
+    """Iterate sweeps until the corner spectra change by less than tol.
+    Returns (env, sweeps_done, delta)."""
+    s_old = corner_spectra(env)
+    delta = math.inf
+    done = 0
+    for _ in range(max_sweeps):
+        env = sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff)
+        done += 1
+        s_new = corner_spectra(env)
+        delta = spectra_delta(s_old, s_new)
+        s_old = s_new
+        if delta < tol:
+            break
+    return env, done, delta
+
+
+# ----------------------------------------------------------------------------
+# Initial environments
+# ----------------------------------------------------------------------------
+def init_identity(Lx, Ly, D):
+    """chi_E = 1, chi_I = D: corners [[1]], first transfer tensor [1,s,i] =
+    delta_si, second [i,s,1] = delta_is, so the merged edge traces the ket and
+    bra virtual legs at the boundary."""
+    one = torch.ones((1, 1), dtype=DT)
+    eye = torch.eye(D, dtype=DT)
+    first = eye.reshape(1, D, D)
+    second = eye.reshape(D, D, 1)
+    env = {}
+    for x in range(Lx):
+        for y in range(Ly):
+            env[(x, y)] = dict(C1=one, C2=one, C3=one, C4=one,
+                               T1k=first, T2k=first, T3b=first, T4b=first,
+                               T1b=second, T2b=second, T3k=second, T4k=second)
+    return env
+
+
+def init_product(Lx, Ly, v):
+    """chi_E = chi_I = 1 boundary with every transfer tensor equal to v on its
+    physical-side leg (fixes the boundary configuration)."""
+    v = torch.as_tensor(v, dtype=DT)
+    D = v.numel()
+    one = torch.ones((1, 1), dtype=DT)
+    t = v.reshape(1, D, 1)
+    env = {}
+    for x in range(Lx):
+        for y in range(Ly):
+            env[(x, y)] = {n: (one if n.startswith("C") else t) for n in NAMES}
+    return env
+
+
+def env_from_numpy(env_np):
+    return {k: {n: torch.as_tensor(v, dtype=DT) for n, v in e.items()} for k, e in env_np.items()}
+
+
+def peps_from_numpy(A_np):
+    Lx, Ly = A_np.shape[:2]
+    return {(x, y): torch.as_tensor(A_np[x, y], dtype=DT) for x in range(Lx) for y in range(Ly)}
+
+
+# ----------------------------------------------------------------------------
+# Observables (Sec. II A, Fig. CTMRG_Method_2; Sec. III Heisenberg energy)
+# ----------------------------------------------------------------------------
+def norm_1site(e, A):
+    """The norm network of Fig. split-transfer-ctmrg for one site."""
+    return ncon("ab,bce,efg,gh,hij,jkm,mn,noq,qrt,tv,vwx,xya,zcyri,zfwok->",
+                e["C1"], e["T1k"], e["T1b"], e["C2"], e["T2k"], e["T2b"], e["C3"],
+                e["T3b"], e["T3k"], e["C4"], e["T4b"], e["T4k"], A, A)
+
+
+def rdm_vertical(env, A, x, y, Lx, Ly):
+    """Two-site reduced density matrix of sites [x,y] (upper) and [x+1,y]
+    (lower): the green patch with both physical legs of ket and bra open.
+    Returns rho[P, Q, P', Q'] (P, Q ket; P', Q' bra), unnormalised."""
+    xp = (x + 1) % Lx
+    e, a = env[(x, y)], A[(x, y)]
+    f, b = env[(xp, y)], A[(xp, y)]
+    top = ncon("ab,bce,efg,gh,hij,jkF,xya,Ewx,PcyKi,RfwBk->EKBFPR",
+               e["C1"], e["T1k"], e["T1b"], e["C2"], e["T2k"], e["T2b"],
+               e["T4k"], e["T4b"], a, a)
+    bot = ncon("xyE,vwx,tv,qrt,noq,mn,jkm,Fij,QKyri,SBwok->EKBFQS",
+               f["T4k"], f["T4b"], f["C4"], f["T3k"], f["T3b"], f["C3"],
+               f["T2b"], f["T2k"], b, b)
+    return ncon("EKBFPR,EKBFQS->PQRS", top, bot)
+
+
+def bond_value(rho, h):
+    """<h> = sum rho[P,Q,P',Q'] h[(P',Q'),(P,Q)] / Tr rho."""
+    p = rho.shape[0]
+    h4 = torch.as_tensor(h, dtype=DT).reshape(p, p, p, p)     # [P',Q',P,Q]
+    num = ncon("PQRS,RSPQ->", rho, h4)
+    den = ncon("PQPQ->", rho)
+    return num / den
+
+
+def energy(env, A, Lx, Ly, h):
+    """Energy per site: (1/(Lx Ly)) sum_{x,y} (e_h[x,y] + e_v[x,y]).
+    Vertical bonds from rdm_vertical; horizontal bonds are vertical bonds of
+    the transposed frame.  Returns (e_site, {(x,y): (e_h, e_v)})."""
+    bonds = {}
+    et, At, lxt, lyt = frame_transpose(env, A, Lx, Ly)
+    tot = 0.0
+    for x in range(Lx):
+        for y in range(Ly):
+            ev = bond_value(rdm_vertical(env, A, x, y, Lx, Ly), h)
+            eh = bond_value(rdm_vertical(et, At, y, x, lxt, lyt), h)
+            bonds[(x, y)] = (eh, ev)
+            tot = tot + eh + ev
+    return tot / (Lx * Ly), bonds
+
+
+def one_site_value(e, A, op):
+    """<op> at one site from its full environment."""
+    N = ncon("ab,bce,efg,gh,hij,jkm,mn,noq,qrt,tv,vwx,xya,Pcyri,Rfwok->PR",
+             e["C1"], e["T1k"], e["T1b"], e["C2"], e["T2k"], e["T2b"], e["C3"],
+             e["T3b"], e["T3k"], e["C4"], e["T4b"], e["T4k"], A, A)
+    op = torch.as_tensor(op, dtype=DT)
+    return ncon("PR,RP->", N, op) / torch.trace(N)
+
+
+def log_kappa(e, A):
+    """ln of the partition function per site, ln(Z11 Z00 / (Z10 Z01)) for a
+    1-site cell: Z11 = full norm network, Z00 = the four corners, Z10 = the
+    column network C1 T1 C2 | C4 T3 C3 with T1 and T3 joined, Z01 = the row
+    network C1 T4 C4 | C2 T2 C3 with T4 and T2 joined."""
+    z11 = norm_1site(e, A)
+    z00 = ncon("ab,bc,cd,da->", e["C1"], e["C2"], e["C3"], e["C4"])
+    z10 = ncon("ab,bce,efg,gh,hn,nfq,qct,ta->",
+               e["C1"], e["T1k"], e["T1b"], e["C2"], e["C3"], e["T3b"], e["T3k"], e["C4"])
+    z01 = ncon("ab,bh,hij,jkm,mn,nv,vkx,xia->",
+               e["C1"], e["C2"], e["T2k"], e["T2b"], e["C3"], e["C4"], e["T4b"], e["T4k"])
+    return torch.log(z11 * z00 / (z10 * z01))

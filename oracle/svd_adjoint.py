@@ -1,0 +1,53 @@
+"""Full square SVD with a Lorentzian-broadened reverse-mode rule (test oracle).
+
+Reverse mode of M = U S V^T for square M with all singular triplets kept in
+the decomposition (truncation happens afterwards by slicing, so cotangents of
+discarded columns are zero).  This is the standard real-SVD adjoint used for
+CTMRG differentiation (the AD approach the paper builds on, Sec. I and
+Sec. III; Liao et al. 2019 and Townsend 2016 for the formula):
+
+    Mbar = U [ (F o (U^T Ubar - Ubar^T U)) S + diag(Sbar)
+               + S (F o (V^T Vbar - Vbar^T V)) ] V^T
+
+with F_ij = 1 / (s_j^2 - s_i^2), here broadened to
+F_ij = (s_j^2 - s_i^2) / ((s_j^2 - s_i^2)^2 + eps_F), eps_F = (eps_rel s_1^2)^2,
+and F_ii = 0: the Lorentzian only acts where |s_j^2 - s_i^2| < eps_rel s_1^2
+(the broadening scale has the units of s^2, so eps_F has those of s^4).  For a square matrix with full U and V there is no
+complement-space term; zero singular values are handled by the same formula.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class BroadenedSVD(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, M: torch.Tensor, eps_rel: float):
+        U, S, Vh = torch.linalg.svd(M, full_matrices=True)
+        V = Vh.transpose(0, 1).contiguous()
+        ctx.save_for_backward(U, S, V)
+        ctx.eps_rel = eps_rel
+        return U, S, V
+
+    @staticmethod
+    def backward(ctx, gU, gS, gV):
+        U, S, V = ctx.saved_tensors
+        n = S.shape[0]
+        s2 = S * S
+        d = s2[None, :] - s2[:, None]                     # d_ij = s_j^2 - s_i^2
+        eps = (ctx.eps_rel * s2[0]) ** 2 if n else 0.0
+        F = d / (d * d + eps) if eps > 0 else torch.where(d != 0, 1.0 / d, torch.zeros_like(d))
+        F.fill_diagonal_(0.0)
+        inner = torch.zeros((n, n), dtype=U.dtype)
+        if gU is not None:
+            inner = inner + (F * (U.T @ gU - gU.T @ U)) * S[None, :]
+        if gV is not None:
+            inner = inner + S[:, None] * (F * (V.T @ gV - gV.T @ V))
+        if gS is not None:
+            inner = inner + torch.diag(gS)
+        return U @ inner @ V.T, None
+
+
+def svd(M: torch.Tensor, eps_rel: float = 1e-12):
+    """Returns U, S, V with M = U diag(S) V^T, S descending."""
+    return BroadenedSVD.apply(M, eps_rel)
