@@ -1,0 +1,145 @@
+/*
+ * splitctm.h -- C ABI of the MI355X (gfx950) split-CTMRG library.
+ *
+ * The library computes, for an infinite PEPS given by a periodic unit cell of
+ * real site tensors A[x][y] (Sec. II A, the coefficient tensor network), the
+ * split-CTMRG environment of Sec. II B (Fig. split-transfer-ctmrg: corners
+ * C1..C4 and, per edge, a ket and a bra transfer tensor joined by an
+ * interlayer bond of dimension chi_I), the projectors of the left move
+ * (Fig. proj_plots_green and App. A: green, teal, yellow, red), the energy of
+ * a nearest-neighbour Hamiltonian (Sec. III) and its gradient with respect to
+ * the site tensors (reverse mode through the whole update, Sec. III).
+ *
+ * Conventions
+ *   - Site tensors: FP64, C order, [Lx][Ly][p][D][D][D][D] with the legs of
+ *     each site ordered (physical, up, left, down, right); x = row, y = column.
+ *   - Environment tensors of one site, in this order ("packed layout"):
+ *       C1[d][r] C2[l][d] C3[u][l] C4[r][u]                   chi_E x chi_E each
+ *       T1k[l][s][r] T1b T2k[u][s][d] T2b T3b[r][s][l] T3k T4b[d][s][u] T4k
+ *     the first tensor along each edge (T1k, T2k, T3b, T4b) is
+ *     [chi_E][D][chi_I], the second (T1b, T2b, T3k, T4k) is [chi_I][D][chi_E];
+ *     sites follow in row-major [x][y] order.  FP64, C order.
+ *   - All device pointers (A, dA, workspace, env buffers) are owned by the
+ *     caller; the library never allocates device memory.  The context object
+ *     itself is host memory, released by ctm_destroy.
+ *   - All work is enqueued on the HIP stream given to ctm_init; calls that
+ *     return host scalars synchronise that stream.  One context per stream;
+ *     calls on one context are not reentrant.
+ *   - Projector SVDs, truncation, normalisation reductions and the final
+ *     energy reduction are always FP64; `contract_prec` sets the precision of
+ *     the tensor-network contractions.
+ *
+ * Errors: every call returns a ctm_status.  CTM_EINVAL = bad argument or
+ * workspace too small (no side effects); CTM_ENUMERIC = non-finite values or a
+ * rank-zero projector matrix; CTM_ENOTCONV = sweep budget exhausted before the
+ * tolerance was met (the environment is still valid); CTM_EDEVICE = a HIP
+ * runtime error.  ctm_strerror never returns NULL.
+ */
+#ifndef SPLITCTM_H
+#define SPLITCTM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CTM_OK = 0,
+  CTM_EINVAL = 1,
+  CTM_ENOMEM = 2,
+  CTM_EDEVICE = 3,
+  CTM_ENOTCONV = 4,
+  CTM_ENUMERIC = 5
+} ctm_status;
+
+typedef enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16X3 = 2 } ctm_precision;
+
+/* Boundary of ctm_init: IDENTITY = chi_E = 1 corners and transfer tensors
+ * that trace the ket and bra virtual legs (independent of A); PRODUCT = every
+ * transfer tensor carries a given vector v on its physical-side leg (fixes the
+ * boundary configuration, e.g. an ordered Ising boundary). A random start is
+ * passed in with ctm_env_import. */
+typedef enum { CTM_INIT_IDENTITY = 0, CTM_INIT_PRODUCT = 1 } ctm_init_mode;
+
+typedef struct {
+  int Lx, Ly;                  /* unit cell: rows, columns */
+  int p, D;                    /* physical and bulk bond dimension */
+  int chi_E, chi_I;            /* environment and interlayer bond dimension */
+  ctm_precision contract_prec; /* bulk contractions */
+  double svd_rel_cutoff;       /* drop singular values below cutoff * s_1 (<= 0: 1e-12) */
+  double svd_adj_eps;          /* Lorentzian broadening of the SVD adjoint (<= 0: 1e-12) */
+  ctm_init_mode init;
+} ctm_config;
+
+typedef struct ctm_ctx ctm_ctx;
+
+/* Bytes of device workspace needed for a context of this configuration.
+ * with_grad != 0 reserves what ctm_energy_grad(n_sweeps, ckpt_every) needs. */
+ctm_status ctm_workspace_size(const ctm_config* cfg, int with_grad, int n_sweeps, int ckpt_every, size_t* bytes);
+
+/* Create a context: copies A (device, FP64, layout above) into the workspace,
+ * writes the initial environment (boundary_vec_host: length D, PRODUCT only,
+ * else NULL) and keeps it as the start environment of ctm_energy_grad. */
+ctm_status ctm_init(const ctm_config* cfg, const double* A_dev, const double* boundary_vec_host, void* workspace_dev,
+                    size_t ws_bytes, void* hip_stream, ctm_ctx** out);
+
+/* Directional sweeps (left, top, right, bottom move; Sec. II B) until the
+ * corner singular values change by less than tol (2-norm, largest over all
+ * corners) or max_sweeps are done.  tol <= 0 runs exactly max_sweeps. */
+ctm_status ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done, double* delta);
+
+/* The four projector pairs of the move in `direction` (0 left, 1 top,
+ * 2 right, 3 bottom) for the cut below row x / row x of the column holding
+ * site [x][y] (in that move's frame), from the current environment, which is
+ * not modified.  out_dev (FP64, device) receives, in order, green P_T, P_B
+ * [chi_E][D][chi_E], teal P_T, P_B [chi_E][D][chi_E], yellow P_T, P_B
+ * [chi_I][D][chi_I] and red P_T, P_B [chi_I][p][D][chi_I]; columns beyond the
+ * kept rank are zero.  trunc_err_host[4] = discarded weight sum_{k>=kept}
+ * s_k^2 / sum s_k^2 of green, teal, yellow, red. */
+ctm_status ctm_projectors(ctm_ctx* ctx, int direction, int x, int y, double* out_dev, double* trunc_err_host);
+size_t ctm_projectors_elems(const ctm_config* cfg);
+
+/* Energy per site of the nearest-neighbour Hamiltonian h (host, FP64,
+ * p^2 x p^2 row-major, rows (s1 s2) bra, columns (s1 s2) ket, s1 = upper or
+ * left site).  e_bonds (host, optional) = [Lx][Ly][2] horizontal, vertical
+ * bond energies of each site. */
+ctm_status ctm_energy(ctm_ctx* ctx, const double* h_host, double* e_site, double* e_bonds);
+
+/* E(A) = energy after exactly n_sweeps sweeps from the start environment, and
+ * dE/dA (device, FP64, layout of A) by reverse mode with the hand-written
+ * adjoints; the environment is checkpointed every ckpt_every sweeps and the
+ * sweeps of each block are recomputed in the backward pass.  The current
+ * environment is left at the state after the n_sweeps sweeps. */
+ctm_status ctm_energy_grad(ctm_ctx* ctx, const double* h_host, int n_sweeps, int ckpt_every, double* e_site,
+                           double* dA_dev);
+
+/* Current environment to / from a device FP64 buffer in the packed layout
+ * (ctm_env_elems doubles).  Import also resets the start environment. */
+size_t ctm_env_elems(const ctm_config* cfg);
+ctm_status ctm_env_export(ctm_ctx* ctx, double* env_dev);
+ctm_status ctm_env_import(ctm_ctx* ctx, const double* env_dev);
+
+/* Counters of the last call: algorithmic GEMM flops issued and Jacobi sweeps. */
+ctm_status ctm_last_stats(ctm_ctx* ctx, double* gemm_flops, double* svd_sweeps);
+
+/* Diagnostics: the kernels behind the calls above, exposed for kernel-level
+ * checks.  ctm_debug_gemm: C[M][N] = op(A) op(B), row-major, prec CTM_FP64
+ * (double) or CTM_FP32 / CTM_BF16X3 (float); transA: A stored K x M, transB: B
+ * stored N x K.  ctm_debug_svd: batch n x n FP64 matrices M (row-major,
+ * consecutive) -> U S V^T, S descending; work = ctm_debug_svd_work_bytes
+ * bytes of device memory.  Both synchronise the stream. */
+ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K, const void* A, const void* B,
+                          void* C, void* hip_stream);
+size_t ctm_debug_svd_work_bytes(int n, int batch);
+ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S, double* V, void* work,
+                         int* sweeps, void* hip_stream);
+
+void ctm_destroy(ctm_ctx* ctx);
+const char* ctm_strerror(ctm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLITCTM_H */

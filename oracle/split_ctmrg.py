@@ -256,6 +256,39 @@ def right_intermediate(env, A, Lx, y, Gr, Yr):
     return C2t, T2kt, T2bt, C3t
 
 
+def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12):
+    """Steps 1-3 of the left move of column y: green / yellow projectors,
+    intermediate environments, teal / red projectors.  Returns
+    (G, Y, TH, R, left intermediate env); G[x], TH[x] belong to the cut
+    (x|x+1), Y[x], R[x] to row x; each is (P_T, P_B, S, k)."""
+    yn = (y + 1) % Ly
+    G, Y, Gr, Yr = _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps)
+    if yn != y:
+        Gr, Yr = _first_projectors(env, A, Lx, yn, chi_E, chi_I, cutoff, adj_eps)[2:]
+    C1t, T4kt, T4bt, C4t = left_intermediate(env, A, Lx, y, G, Y)
+    C2t, T2kt, T2bt, C3t = right_intermediate(env, A, Lx, yn, Gr, Yr)
+    TH, R = {}, {}
+    for x in range(Lx):
+        xp = (x + 1) % Lx
+        m, mp = env[(x, y)], env[(xp, y)]          # middle: bra part of column y
+        n, np_ = env[(x, yn)], env[(xp, yn)]       # middle: ket part of column y+1
+        b, bp = A[(x, y)], A[(xp, y)]
+        k, kp = A[(x, yn)], A[(xp, yn)]
+        rT = ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
+                  C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
+                  T2kt[x], T2bt[x])
+        rB = ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
+                  T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
+                  T2kt[xp], T2bt[xp])
+        TH[x] = projectors(rT, rB, 2, chi_E, cutoff, adj_eps)
+        sT = ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
+                  C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
+        sB = ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
+                  T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
+        R[x] = projectors(sT, sB, 3, chi_I, cutoff, adj_eps)
+    return G, Y, TH, R, (C1t, T4kt, T4bt, C4t)
+
+
 def left_move(env: Dict, A: Dict, Lx: int, Ly: int, chi_E: int, chi_I: int,
               cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None):
     """Absorb every column of the cell into the left environment, in place.
@@ -273,30 +306,8 @@ def left_move(env: Dict, A: Dict, Lx: int, Ly: int, chi_E: int, chi_I: int,
       4. bra half-step: new C1, T4k, T4b, C4 of site [x, y+1], normalised."""
     for y in range(Ly):
         yn = (y + 1) % Ly
-        G, Y, Gr, Yr = _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps)
-        if yn != y:
-            Gr, Yr = _first_projectors(env, A, Lx, yn, chi_E, chi_I, cutoff, adj_eps)[2:]
-        C1t, T4kt, T4bt, C4t = left_intermediate(env, A, Lx, y, G, Y)
-        C2t, T2kt, T2bt, C3t = right_intermediate(env, A, Lx, yn, Gr, Yr)
-        TH, R = {}, {}
-        for x in range(Lx):
-            xp = (x + 1) % Lx
-            m, mp = env[(x, y)], env[(xp, y)]          # middle: bra part of column y
-            n, np_ = env[(x, yn)], env[(xp, yn)]       # middle: ket part of column y+1
-            b, bp = A[(x, y)], A[(xp, y)]
-            k, kp = A[(x, yn)], A[(xp, yn)]
-            rT = ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
-                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
-                      T2kt[x], T2bt[x])
-            rB = ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
-                      T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
-                      T2kt[xp], T2bt[xp])
-            TH[x] = projectors(rT, rB, 2, chi_E, cutoff, adj_eps)
-            sT = ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
-                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
-            sB = ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
-                      T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
-            R[x] = projectors(sT, sB, 3, chi_I, cutoff, adj_eps)
+        G, Y, TH, R, (C1t, T4kt, T4bt, C4t) = column_projectors(
+            env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps)
         new = {}
         for x in range(Lx):
             e, a = env[(x, y)], A[(x, y)]

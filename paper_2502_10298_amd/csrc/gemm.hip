@@ -1,0 +1,286 @@
+// Batched GEMM on the CDNA4 matrix cores (gfx950).
+//
+// Every contraction of the split-CTMRG networks is reshaped into a GEMM
+// C = alpha op(A) op(B) + beta C on row-major operands.  The kernels tile C in
+// 64 x 64 blocks per workgroup of four 64-wide wavefronts (2 x 2 waves, each
+// owning a 32 x 32 quadrant = 2 x 2 MFMA 16 x 16 tiles) and stage the A and B
+// panels through LDS, k-major, so that the MFMA operand fetches of a wave read
+// 16 consecutive LDS words per k row.
+//
+//   F64     v_mfma_f64_16x16x4_f64     (FP64 parity path)
+//   F32     v_mfma_f32_16x16x4_f32
+//   BF16X3  v_mfma_f32_16x16x32_bf16 on split operands a = a_hi + a_lo
+//           (bf16 each), accumulating a_hi b_hi + a_hi b_lo + a_lo b_hi in FP32
+//           (the product a_lo b_lo, of relative size 2^-16, is dropped).
+//
+// MFMA lane layouts used (16x16xK, 64 lanes):
+//   A operand: lane l holds A[l % 16][kblk(l / 16)]
+//   B operand: lane l holds B[kblk(l / 16)][l % 16]
+//   D (4 per lane): D[4 (l / 16) + r][l % 16], r = 0..3 for f32 and bf16,
+//                   D[4 r + l / 16][l % 16] for f64 (measured on gfx950)
+// with kblk = one k (x4 f32/f64) or eight consecutive k (x32 bf16); A and B
+// use the same k slot order, so only the output layout matters.
+#include "kernels.hpp"
+
+namespace sctm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+static constexpr int BM = 64, BN = 64;
+
+template <typename T, typename V4>
+__device__ inline V4 mfma_step(T a, T b, V4 c);
+
+template <>
+__device__ inline d4 mfma_step<double, d4>(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ inline f4 mfma_step<float, f4>(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 / FP32: BK = 16 (four MFMA k-steps of 4)
+// ---------------------------------------------------------------------------
+template <typename T, typename V4, bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
+                                                   const T* __restrict__ A, long lda, long sA,
+                                                   const T* __restrict__ B, long ldb, long sB, T beta,
+                                                   T* __restrict__ C, long ldc, long sC) {
+  constexpr int BK = 16;
+  __shared__ T As[BK][BM + 4];
+  __shared__ T Bs[BK][BN + 4];
+  const long bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  const int bm = blockIdx.y * BM, bn = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  V4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    if (!TA) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int r = (tid >> 4) + 16 * i, c = tid & 15;
+        int m = bm + r, k = k0 + c;
+        As[c][r] = (m < M && k < K) ? A[(long)m * lda + k] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int r = (tid >> 6) + 4 * i, c = tid & 63;
+        int k = k0 + r, m = bm + c;
+        As[r][c] = (m < M && k < K) ? A[(long)k * lda + m] : T(0);
+      }
+    }
+    if (!TB) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int r = (tid >> 6) + 4 * i, c = tid & 63;
+        int k = k0 + r, n = bn + c;
+        Bs[r][c] = (n < N && k < K) ? B[(long)k * ldb + n] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int r = (tid >> 4) + 16 * i, c = tid & 15;
+        int n = bn + r, k = k0 + c;
+        Bs[c][r] = (n < N && k < K) ? B[(long)n * ldb + k] : T(0);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      T a0 = As[kr][wm * 32 + (lane & 15)];
+      T a1 = As[kr][wm * 32 + 16 + (lane & 15)];
+      T b0 = Bs[kr][wn * 32 + (lane & 15)];
+      T b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+      acc[0][0] = mfma_step<T, V4>(a0, b0, acc[0][0]);
+      acc[0][1] = mfma_step<T, V4>(a0, b1, acc[0][1]);
+      acc[1][0] = mfma_step<T, V4>(a1, b0, acc[1][0]);
+      acc[1][1] = mfma_step<T, V4>(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // f64 16x16x4: D[4 r + l / 16][l % 16]; f32 16x16x4: D[4 (l / 16) + r][l % 16]
+        const int row = sizeof(T) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        int m = bm + wm * 32 + ti * 16 + row;
+        int n = bn + wn * 32 + tj * 16 + (lane & 15);
+        if (m < M && n < N) {
+          T v = alpha * acc[ti][tj][r];
+          long o = (long)m * ldc + n;
+          C[o] = (beta == T(0)) ? v : v + beta * C[o];
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3: FP32 operands split into bf16 hi + lo in the LDS staging; BK = 32.
+// ---------------------------------------------------------------------------
+__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;                  // round to nearest even
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(int M, int N, int K, float alpha,
+                                                          const float* __restrict__ A, long lda, long sA,
+                                                          const float* __restrict__ B, long ldb, long sB,
+                                                          float beta, float* __restrict__ C, long ldc,
+                                                          long sC) {
+  constexpr int BK = 32;
+  // m-major rows of 32 k (bf16) for A, n-major rows of 32 k for B: one lane
+  // fetches 8 consecutive k of one row as a 16-byte vector.
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][BK + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[BM][BK + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][BK + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN][BK + 8];
+  const long bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  const int bm = blockIdx.y * BM, bn = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    // A panel: 64 rows (m) x 32 k = 2048 values, 8 per thread
+    if (!TA) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        int r = (tid >> 5) + 8 * i, c = tid & 31;
+        int m = bm + r, k = k0 + c;
+        float v = (m < M && k < K) ? A[(long)m * lda + k] : 0.f;
+        split_bf16(v, Ah[r][c], Al[r][c]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        int r = (tid >> 6) + 4 * i, c = tid & 63;   // r = k, c = m
+        int k = k0 + r, m = bm + c;
+        float v = (m < M && k < K) ? A[(long)k * lda + m] : 0.f;
+        split_bf16(v, Ah[c][r], Al[c][r]);
+      }
+    }
+    if (!TB) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        int r = (tid >> 6) + 4 * i, c = tid & 63;   // r = k, c = n
+        int k = k0 + r, n = bn + c;
+        float v = (n < N && k < K) ? B[(long)k * ldb + n] : 0.f;
+        split_bf16(v, Bh[c][r], Bl[c][r]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        int r = (tid >> 5) + 8 * i, c = tid & 31;   // r = n, c = k
+        int n = bn + r, k = k0 + c;
+        float v = (n < N && k < K) ? B[(long)n * ldb + k] : 0.f;
+        split_bf16(v, Bh[r][c], Bl[r][c]);
+      }
+    }
+    __syncthreads();
+    const int kq = 8 * (lane >> 4);
+    bf8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      ah[t] = *reinterpret_cast<const bf8*>(&Ah[wm * 32 + t * 16 + (lane & 15)][kq]);
+      al[t] = *reinterpret_cast<const bf8*>(&Al[wm * 32 + t * 16 + (lane & 15)][kq]);
+      bh[t] = *reinterpret_cast<const bf8*>(&Bh[wn * 32 + t * 16 + (lane & 15)][kq]);
+      bl[t] = *reinterpret_cast<const bf8*>(&Bl[wn * 32 + t * 16 + (lane & 15)][kq]);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ti], bh[tj], acc[ti][tj], 0, 0, 0);
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bl[tj], acc[ti][tj], 0, 0, 0);
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bh[tj], acc[ti][tj], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int m = bm + wm * 32 + ti * 16 + 4 * (lane >> 4) + r;
+        int n = bn + wn * 32 + tj * 16 + (lane & 15);
+        if (m < M && n < N) {
+          float v = alpha * acc[ti][tj][r];
+          long o = (long)m * ldc + n;
+          C[o] = (beta == 0.f) ? v : v + beta * C[o];
+        }
+      }
+}
+
+static dim3 gemm_grid(int M, int N, int batch) {
+  return dim3((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+}
+
+hipError_t gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double alpha,
+                    const double* A, long lda, long sA, const double* B, long ldb, long sB,
+                    double beta, double* C, long ldc, long sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 g = gemm_grid(M, N, batch);
+  if (!tA && !tB)
+    hipLaunchKernelGGL((gemm_kernel<double, d4, false, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else if (tA && !tB)
+    hipLaunchKernelGGL((gemm_kernel<double, d4, true, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else if (!tA && tB)
+    hipLaunchKernelGGL((gemm_kernel<double, d4, false, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else
+    hipLaunchKernelGGL((gemm_kernel<double, d4, true, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  return hipGetLastError();
+}
+
+hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, int K, float alpha,
+                    const float* A, long lda, long sA, const float* B, long ldb, long sB, float beta,
+                    float* C, long ldc, long sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 g = gemm_grid(M, N, batch);
+  if (mode == Prec::BF16X3) {
+    if (!tA && !tB)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    else if (tA && !tB)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    else if (!tA && tB)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    else
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    return hipGetLastError();
+  }
+  if (!tA && !tB)
+    hipLaunchKernelGGL((gemm_kernel<float, f4, false, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else if (tA && !tB)
+    hipLaunchKernelGGL((gemm_kernel<float, f4, true, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else if (!tA && tB)
+    hipLaunchKernelGGL((gemm_kernel<float, f4, false, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else
+    hipLaunchKernelGGL((gemm_kernel<float, f4, true, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  return hipGetLastError();
+}
+
+}  // namespace sctm

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every case prints what it runs before touching the GPU.  Sizes span several
+MFMA tiles and ragged tails; the headline workload is covered by sampled
+properties in test_gpu_workloads.py.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import grad as og
+from oracle import split_ctmrg as sc
+from paper_2502_10298_amd import binding as b
+from paper_2502_10298_amd import inputs as inp
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# kernels
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("shape", [(70, 45, 33), (300, 260, 190), (1, 129, 64), (257, 3, 1000)])
+@pytest.mark.parametrize("tA,tB", [(False, False), (True, False), (False, True), (True, True)])
+def test_gemm(prec, tol, shape, tA, tB):
+    M, N, K = shape
+    _say("gemm", prec, shape, tA, tB)
+    g = torch.Generator(device="cpu").manual_seed(M * 7 + N)
+    A = torch.randn((K, M) if tA else (M, K), generator=g, dtype=torch.float64)
+    B = torch.randn((N, K) if tB else (K, N), generator=g, dtype=torch.float64)
+    ref = (A.T if tA else A) @ (B.T if tB else B)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    C = b.debug_gemm(A.to(DEV, dt), B.to(DEV, dt), tA, tB, prec).double().cpu()
+    err = (C - ref).norm() / ref.norm()
+    assert err < tol, float(err)
+
+
+@pytest.mark.parametrize("n,batch", [(5, 1), (33, 2), (100, 3), (257, 1)])
+def test_jacobi_svd(n, batch):
+    _say("svd", n, batch)
+    g = torch.Generator().manual_seed(n)
+    M = torch.randn(batch, n, n, generator=g, dtype=torch.float64)
+    M[0, :, n // 3] = 0.0             # a zero column: rank deficient
+    if n > 4:
+        M[-1] = M[-1] * torch.logspace(0, -9, n, dtype=torch.float64)[None, :]   # wide spectrum
+    U, S, V, sweeps = b.debug_svd(M.to(DEV))
+    U, S, V = U.cpu(), S.cpu(), V.cpu()
+    for i in range(batch):
+        ref = torch.linalg.svdvals(M[i])
+        assert torch.allclose(S[i], ref, rtol=0, atol=1e-13 * float(ref[0]))
+        rec = (U[i] * S[i]) @ V[i].T
+        assert (rec - M[i]).norm() < 2e-12 * M[i].norm()
+        assert torch.allclose(V[i].T @ V[i], torch.eye(n, dtype=torch.float64), atol=1e-12)
+        r = int((S[i] > 1e-13 * S[i][0]).sum())
+        Ur = U[i][:, :r]
+        assert torch.allclose(Ur.T @ Ur, torch.eye(r, dtype=torch.float64), atol=1e-10)
+    assert sweeps < 60
+
+
+# ---------------------------------------------------------------------------
+# whole path, FP64, against the oracle
+# ---------------------------------------------------------------------------
+def _oracle_run(A_np, chi, sweeps, env0=None):
+    Lx, Ly = A_np.shape[:2]
+    A = sc.peps_from_numpy(A_np)
+    env = sc.env_from_numpy(env0) if env0 is not None else sc.init_identity(Lx, Ly, A_np.shape[3])
+    for _ in range(sweeps):
+        env = sc.sweep(env, A, Lx, Ly, chi, chi)
+    return env, A
+
+
+def test_energy_parity_d2_chi8_fp64():
+    """D=2, chi=8, 30 sweeps from the identity boundary, Heisenberg energy in
+    the rotated frame: GPU FP64 equals the oracle to 1e-10 relative."""
+    A_np = inp.workload_peps("d2_D2_chi8")
+    h = inp.heisenberg_h_rotated()
+    _say("energy d2_D2_chi8 fp64")
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 8, prec="fp64")
+    obj.sweep(30)
+    e_gpu, bonds = obj.energy(h)
+    env, A = _oracle_run(A_np, 8, 30)
+    e_ref, bref = sc.energy(env, A, 1, 1, h)
+    assert abs(e_gpu - float(e_ref)) <= 1e-10 * abs(float(e_ref)), (e_gpu, float(e_ref))
+    assert abs(bonds[0, 0, 0] - float(bref[(0, 0)][0])) <= 1e-10
+    assert abs(bonds[0, 0, 1] - float(bref[(0, 0)][1])) <= 1e-10
+
+
+def test_env_and_projectors_parity_fp64():
+    """After a few sweeps the exported environment (corner spectra) and the
+    four projector pairs of every direction agree with the oracle computed
+    from that same environment."""
+    A_np = inp.peps_gaussian(77, 1, 1, 2, 2)
+    chi = 6
+    _say("projectors d2 chi6")
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec="fp64")
+    obj.sweep(3)
+    flat = obj.env_export().cpu().numpy()
+    env = sc.env_from_numpy(inp.unpack_env(flat, 1, 1, 2, chi, chi))
+    env_ref, A = _oracle_run(A_np, chi, 3)
+    for c in ("C1", "C2", "C3", "C4"):
+        s_gpu = torch.linalg.svdvals(env[(0, 0)][c])
+        s_ref = torch.linalg.svdvals(env_ref[(0, 0)][c])
+        n = min(len(s_gpu), len(s_ref))
+        assert torch.allclose(s_gpu[:n], s_ref[:n], atol=1e-11)
+    for direction in range(4):
+        P, te = obj.projectors(direction, 0, 0)
+        e2, a2, lx, ly = sc.to_frame(["left", "top", "right", "bottom"][direction], env, A, 1, 1)
+        G, Y, TH, R, _ = sc.column_projectors(e2, a2, lx, ly, 0, chi, chi)
+        for nm, pr in (("green", G[0]), ("teal", TH[0]), ("yellow", Y[0]), ("red", R[0])):
+            k = pr[3]
+            for j, side in ((0, "_T"), (1, "_B")):
+                ref = pr[j]
+                got = P[nm + side].cpu()
+                got = got[..., :k].reshape(ref.shape)
+                scale = float(ref.abs().max())
+                assert torch.allclose(got, ref, atol=1e-8 * scale, rtol=0), (direction, nm, side)
+            assert float(P[nm + "_T"].cpu()[..., k:].abs().max() if k < P[nm + "_T"].shape[-1] else 0.0) == 0.0
+
+
+def test_cell_2x2_parity_fp64():
+    """2x2 cell of four different tensors (D=2, chi=6): every bond energy."""
+    A_np = inp.peps_gaussian(91, 2, 2, 2, 2)
+    h = inp.heisenberg_h()
+    _say("cell2x2 d2 chi6 fp64")
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 6, prec="fp64")
+    obj.sweep(4)
+    e_gpu, bonds = obj.energy(h)
+    env, A = _oracle_run(A_np, 6, 4)
+    e_ref, bref = sc.energy(env, A, 2, 2, h)
+    assert abs(e_gpu - float(e_ref)) <= 1e-10 * abs(float(e_ref))
+    for (x, y), (eh, ev) in bref.items():
+        assert abs(bonds[x, y, 0] - float(eh)) <= 1e-9 and abs(bonds[x, y, 1] - float(ev)) <= 1e-9
+
+
+def test_gradient_parity_fp64():
+    """dE/dA from the hand-written adjoints equals the oracle's autograd
+    gradient (2 sweeps from a random full-rank start, D=2, chi=4)."""
+    A_np = inp.peps_gaussian(11, 1, 1, 2, 2)
+    chi, ns = 4, 2
+    env0 = inp.random_env(5, 1, 1, 2, chi, chi)
+    h = inp.heisenberg_h_rotated()
+    _say("gradient d2 chi4 fp64")
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec="fp64", with_grad=True, n_sweeps=ns, ckpt_every=1)
+    obj.env_import(torch.tensor(inp.pack_env(env0, 1, 1, 2, chi, chi), device=DEV))
+    e_gpu, dA = obj.energy_grad(h, ns, 1)
+    e_ref, g_ref = og.energy_and_grad(A_np, env0, chi, chi, ns, h)
+    assert abs(e_gpu - e_ref) <= 1e-10 * abs(e_ref)
+    g = dA.cpu().numpy()
+    assert np.linalg.norm(g - g_ref) <= 1e-8 * np.linalg.norm(g_ref)
+
+
+def test_gradient_checkpoint_blocks_agree():
+    """Checkpointing every sweep or once for all sweeps gives the same gradient."""
+    A_np = inp.peps_gaussian(12, 1, 1, 2, 2)
+    chi, ns = 4, 3
+    env0 = torch.tensor(inp.pack_env(inp.random_env(6, 1, 1, 2, chi, chi), 1, 1, 2, chi, chi), device=DEV)
+    h = inp.heisenberg_h_rotated()
+    _say("gradient checkpoint blocks")
+    out = []
+    for k in (1, 3, 2):
+        obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec="fp64", with_grad=True, n_sweeps=ns, ckpt_every=k)
+        obj.env_import(env0)
+        out.append(obj.energy_grad(h, ns, k))
+    for e, g in out[1:]:
+        assert abs(e - out[0][0]) < 1e-13
+        assert torch.allclose(g, out[0][1], atol=1e-11 * float(out[0][1].abs().max()))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5)])
+def test_mixed_precision_energy(prec, tol):
+    """FP32 contractions with FP64 projectors: energy within 1e-6 relative of
+    the FP64 oracle.  BF16x3 (two-term bf16 split, three products) carries a
+    2^-17 operand error; its measured energy error is about 1.3e-5."""
+    A_np = inp.workload_peps("d2_D2_chi8")
+    h = inp.heisenberg_h_rotated()
+    _say("energy d2_D2_chi8", prec)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 8, prec=prec)
+    obj.sweep(30)
+    e_gpu, _ = obj.energy(h)
+    env, A = _oracle_run(A_np, 8, 30)
+    e_ref, _ = sc.energy(env, A, 1, 1, h)
+    assert abs(e_gpu - float(e_ref)) <= tol * abs(float(e_ref)), (e_gpu, float(e_ref))
+
+
+# ---------------------------------------------------------------------------
+# error paths (forced from the host; every kernel exits normally)
+# ---------------------------------------------------------------------------
+def test_workspace_too_small_is_einval():
+    A = torch.tensor(inp.peps_gaussian(1, 1, 1, 2, 2), device=DEV)
+    _say("workspace too small")
+    with pytest.raises(b.CtmError) as ei:
+        b.SplitCTM(A, 8, workspace_bytes=1024)
+    assert ei.value.status == b.CTM_EINVAL
+
+
+def test_nan_input_is_enumeric():
+    A_np = inp.peps_gaussian(2, 1, 1, 2, 2)
+    A_np[0, 0, 0, 0, 0, 0, 0] = np.nan
+    _say("nan input")
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 6)
+    st, n, d = obj.sweep(2, tol=1e-8, check=False)
+    assert st == b.CTM_ENUMERIC
+
+
+def test_not_converged_is_reported():
+    A_np = inp.peps_gaussian(3, 1, 1, 2, 2)
+    _say("not converged")
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 6)
+    st, n, d = obj.sweep(1, tol=1e-300, check=False)
+    assert st == b.CTM_ENOTCONV and n == 1
+    e, _ = obj.energy(inp.heisenberg_h())   # environment still usable
+    assert math.isfinite(e)

@@ -1,0 +1,49 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every symbol the header declares, and its dry-run workspace planner walks the
+whole contraction plan (every network's index bookkeeping) for each workload."""
+import os
+import re
+
+import pytest
+
+from paper_2502_10298_amd import binding as b
+from paper_2502_10298_amd import inputs as inp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "splitctm.h")).read()
+    return sorted(set(re.findall(r"\b(ctm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = b.lib()
+    names = _declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(b.EXPORTED) <= set(names)
+
+
+def test_strerror_never_null():
+    for s in range(-1, 8):
+        assert isinstance(b.strerror(s), str) and b.strerror(s)
+
+
+@pytest.mark.parametrize("name", list(inp.WORKLOADS))
+def test_dry_run_workspace_plan(name):
+    w = inp.WORKLOADS[name]
+    cfg = b.make_config(w["Lx"], w["Ly"], w["p"], w["D"], w["chi"], w["chi"],
+                        "fp64" if w["prec"] == "fp64" else "fp32")
+    fwd = b.workspace_size(cfg)
+    grad = b.workspace_size(cfg, True, w.get("sweeps") or 5, w.get("ckpt", 1))
+    assert 0 < fwd <= grad < 200 * 2**30
+
+
+def test_invalid_configs_rejected():
+    bad = [b.make_config(0, 1, 2, 2, 8, 8), b.make_config(1, 1, 2, 4, 8, 2),   # chi_I < D with identity
+           b.make_config(1, 1, 2, 2, 0, 8)]
+    for cfg in bad:
+        with pytest.raises(b.CtmError):
+            b.workspace_size(cfg)
