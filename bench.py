@@ -1,0 +1,188 @@
+"""Throughput of the split-CTMRG hot path on one MI355X.
+
+One step = one energy + gradient evaluation at the headline workload (2x2
+unit cell of four distinct real tensors, p = 2, D = 8, chi_E = chi_I = 128,
+BF16x3 contractions with FP32 accumulation, FP64 projectors): `--grad-sweeps`
+split-CTMRG sweeps from the current (pre-converged) environment with
+checkpoints every `--ckpt` sweeps, the nearest-neighbour Heisenberg energy,
+and dE/dA by the hand-written reverse pass.  Forward-only sweeps/s is timed
+separately on the same context.  Inputs are seeded synthetic tensors already
+resident in HBM.
+
+Prints one JSON line (see the keys below); `roofline` is taken from the
+library's own HIP-event timing of the dominant kernel class over the timed
+steps, `cpu_baseline` from the FP64 CPU oracle on a bounded sample (one
+column of one left move at the same sizes).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "cell2x2_d2_D8_chi128_grad"
+METRIC = "split-CTMRG sweeps/s + energy-grad evals/s at D=8,χ=128; MFMA fraction"
+
+# Published MI355X dense peaks (TFLOP/s).  A BF16x3 product issues three BF16
+# MFMA products per FP32-class product, so its algorithmic peak is a third of
+# the BF16 one.
+PEAKS = {
+    "gemm_fp64": (78.6, "fp64 MFMA"),
+    "gemm_fp32": (157.3, "fp32 MFMA"),
+    "gemm_bf16x3": (2500.0 / 3.0, "bf16 MFMA 2500 / 3 products"),
+    "jacobi_round": (78.6, "fp64 MFMA"),
+}
+
+
+def say(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grad-sweeps", type=int, default=4)
+    ap.add_argument("--ckpt", type=int, default=2)
+    ap.add_argument("--pre-sweeps", type=int, default=6, help="untimed sweeps that converge the start environment")
+    ap.add_argument("--fwd-sweeps", type=int, default=4, help="timed forward-only sweeps for sweeps/s")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def cpu_baseline(threads: int) -> dict:
+    """The FP64 oracle on one column of one left move (projectors of every
+    colour and the new C1, T4k, T4b, C4 of both rows) at D = 8, chi = 128,
+    scaled to sweeps/s: a 2x2-cell sweep is 4 moves x 2 columns."""
+    import torch
+    from oracle import split_ctmrg as sc
+    from paper_2502_10298_amd import inputs as inp
+
+    if threads > 0:
+        torch.set_num_threads(threads)
+    used = torch.get_num_threads()
+    w = inp.WORKLOADS[WORKLOAD]
+    env = sc.env_from_numpy(inp.random_env(7, w["Lx"], w["Ly"], w["D"], w["chi"], w["chi"]))
+    A = sc.peps_from_numpy(inp.workload_peps(WORKLOAD))
+    t0 = time.perf_counter()
+    sc.left_move_column(env, A, w["Lx"], w["Ly"], 0, w["chi"], w["chi"])
+    dt = time.perf_counter() - t0
+    per_sweep = dt * 4 * w["Ly"]
+    return {"value": 1.0 / per_sweep, "unit": "sweeps/s", "cores": used, "kind": "oracle",
+            "sample": f"one column of one left move (2 site-moves) at 2x2, D=8, chi=128, FP64, "
+                      f"{dt:.1f} s, scaled x{4 * w['Ly']} to one sweep"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the split-CTMRG path "
+              "runs on a single MI355X; see the sharding notes in the design document.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2502_10298_amd import binding as b
+    from paper_2502_10298_amd import inputs as inp
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = inp.WORKLOADS[WORKLOAD]
+    chi = w["chi"]
+    dev = torch.device("cuda:0")
+    A = torch.tensor(inp.workload_peps(WORKLOAD), device=dev)
+    h = inp.workload_h(WORKLOAD)
+    obj = b.SplitCTM(A, chi, chi, prec=w["prec"], with_grad=True, n_sweeps=args.grad_sweeps,
+                     ckpt_every=args.ckpt)
+
+    # untimed: converge the start environment (an optimisation step starts from
+    # the previous step's environment)
+    st, n, delta = obj.sweep(args.pre_sweeps)
+    obj.env_import(obj.env_export())
+    torch.cuda.synchronize()
+    say(f"start environment: {n} sweeps, corner-spectrum change {delta:.2e}")
+
+    for i in range(args.warmup):
+        obj.energy_grad(h, args.grad_sweeps, args.ckpt)
+        say(f"warmup step {i} done")
+    obj.env_import(obj.env_export())
+    torch.cuda.synchronize()
+
+    obj.kernel_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e = None
+    for i in range(args.steps):
+        e, dA = obj.energy_grad(h, args.grad_sweeps, args.ckpt)
+        say(f"timed step {i} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = obj.kernel_timing()
+    obj.kernel_timing_enable(False)
+    dt = t1 - t0
+    evals_per_s = args.steps / dt
+    gnorm = float(dA.norm())
+
+    # forward-only sweeps/s on the same context
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    obj.sweep(args.fwd_sweeps)
+    torch.cuda.synchronize()
+    sweeps_per_s = args.fwd_sweeps / (time.perf_counter() - s0)
+    say(f"forward sweeps: {sweeps_per_s:.3f} sweeps/s")
+
+    dom = max(timing, key=lambda k: timing[k][0])
+    ms, launches, work = timing[dom]
+    peak, basis = PEAKS[dom]
+    achieved = (work / launches) / (ms / launches * 1e-3) / 1e12 if launches else 0.0
+    total_ms = sum(v[0] for v in timing.values())
+    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None, "kernel": dom, "peak_basis": basis,
+            "launches": int(launches), "avg_launch_us": 1e3 * ms / launches if launches else None,
+            "share_of_timed_kernels": ms / total_ms if total_ms else None,
+            "classes": {k: {"ms": v[0], "launches": int(v[1]),
+                            "tflops": (v[2] / (v[0] * 1e-3) / 1e12) if v[0] else None}
+                        for k, v in timing.items()}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        say("CPU oracle sample")
+        cpu = cpu_baseline(args.cpu_threads)
+
+    out = {
+        "metric": METRIC,
+        "value": evals_per_s,
+        "unit": "energy-grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "cell": "2x2", "p": 2, "D": 8, "chi_E": chi, "chi_I": chi,
+                   "sweeps_per_eval": args.grad_sweeps, "ckpt_every": args.ckpt,
+                   "pre_sweeps": args.pre_sweeps},
+        "sweeps_per_s": sweeps_per_s,
+        "energy": e,
+        "grad_norm": gnorm,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    obj.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -128,12 +128,24 @@ ctm_status ctm_last_stats(ctm_ctx* ctx, double* gemm_flops, double* svd_sweeps);
  * (double) or CTM_FP32 / CTM_BF16X3 (float); transA: A stored K x M, transB: B
  * stored N x K.  ctm_debug_svd: batch n x n FP64 matrices M (row-major,
  * consecutive) -> U S V^T, S descending; work = ctm_debug_svd_work_bytes
- * bytes of device memory.  Both synchronise the stream. */
+ * bytes of device memory; *sweeps in: sweep cap (<= 0: 60), out: sweeps run.
+ * Both synchronise the stream. */
 ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K, const void* A, const void* B,
                           void* C, void* hip_stream);
 size_t ctm_debug_svd_work_bytes(int n, int batch);
 ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S, double* V, void* work,
                          int* sweeps, void* hip_stream);
+
+/* Kernel timing (diagnostics): when enabled, every launch of the timed kernel
+ * classes made by this context is bracketed by HIP events on the context's
+ * stream; after each call the elapsed times are added up per class.
+ * Enabling (or disabling) resets the totals.  Classes: 0 GEMM FP64, 1 GEMM
+ * FP32, 2 GEMM BF16x3, 3 Jacobi round of the projector SVD.  *ms = summed
+ * kernel time, *launches = number of launches, *work = algorithmic flops of
+ * those launches (GEMM: 2 M N K per product; Jacobi round: the Gram matrix and
+ * the rotation of G and V for every block pair of the round). */
+ctm_status ctm_kernel_timing_enable(ctm_ctx* ctx, int on);
+ctm_status ctm_kernel_timing(ctm_ctx* ctx, int kernel_class, double* ms, double* launches, double* work);
 
 void ctm_destroy(ctm_ctx* ctx);
 const char* ctm_strerror(ctm_status s);

@@ -291,9 +291,17 @@ def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-
 
 def left_move(env: Dict, A: Dict, Lx: int, Ly: int, chi_E: int, chi_I: int,
               cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None):
-    """Absorb every column of the cell into the left environment, in place.
+    """Absorb every column of the cell into the left environment, in place,
+    one column after the other (left_move_column)."""
+    for y in range(Ly):
+        left_move_column(env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps, info)
 
-    Column y, every row x:
+
+def left_move_column(env: Dict, A: Dict, Lx: int, Ly: int, y: int, chi_E: int, chi_I: int,
+                     cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None):
+    """Absorb column y into the left environment of column y+1, in place.
+
+    Every row x:
       1. green / yellow projectors of column y (ket layer) and the mirrored
          pair of column y+1 (bra layer of the right environment);
       2. ket half-step: intermediate left environment of column y, and the
@@ -304,34 +312,33 @@ def left_move(env: Dict, A: Dict, Lx: int, Ly: int, chi_E: int, chi_I: int,
          (App. A: these half networks contain the first projectors; the b
          legs are (D, chi_E) for teal and (D, p, chi_I) for red);
       4. bra half-step: new C1, T4k, T4b, C4 of site [x, y+1], normalised."""
-    for y in range(Ly):
-        yn = (y + 1) % Ly
-        G, Y, TH, R, (C1t, T4kt, T4bt, C4t) = column_projectors(
-            env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps)
-        new = {}
+    yn = (y + 1) % Ly
+    G, Y, TH, R, (C1t, T4kt, T4bt, C4t) = column_projectors(
+        env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps)
+    new = {}
+    for x in range(Lx):
+        e, a = env[(x, y)], A[(x, y)]
+        ThT_up, ThB_up = TH[(x - 1) % Lx][0], TH[(x - 1) % Lx][1]
+        ThT_dn, ThB_dn = TH[x][0], TH[x][1]
+        RT, RB = R[x][0], R[x][1]
+        new[x] = dict(
+            C1=_normalize(ncon("ge,efR,gfD->DR", C1t[x], e["T1b"], ThT_up)),
+            T4k=_normalize(ncon("gSYP,gWU,YPWD->DSU", T4kt[x], ThB_up, RT)),
+            T4b=_normalize(ncon("Ywg,PWwBs,YPWU,gBD->DsU", T4bt[x], a, RB, ThT_dn)),
+            C4=_normalize(ncon("gq,Roq,goU->RU", C4t[x], e["T3b"], ThB_dn)),
+        )
+    if info is not None:
         for x in range(Lx):
-            e, a = env[(x, y)], A[(x, y)]
-            ThT_up, ThB_up = TH[(x - 1) % Lx][0], TH[(x - 1) % Lx][1]
-            ThT_dn, ThB_dn = TH[x][0], TH[x][1]
-            RT, RB = R[x][0], R[x][1]
-            new[x] = dict(
-                C1=_normalize(ncon("ge,efR,gfD->DR", C1t[x], e["T1b"], ThT_up)),
-                T4k=_normalize(ncon("gSYP,gWU,YPWD->DSU", T4kt[x], ThB_up, RT)),
-                T4b=_normalize(ncon("Ywg,PWwBs,YPWU,gBD->DsU", T4bt[x], a, RB, ThT_dn)),
-                C4=_normalize(ncon("gq,Roq,goU->RU", C4t[x], e["T3b"], ThB_dn)),
-            )
-        if info is not None:
-            for x in range(Lx):
-                for tag, pr in (("green", G[x]), ("yellow", Y[x]), ("teal", TH[x]), ("red", R[x])):
-                    S = pr[2]
-                    tot = float((S * S).sum())
-                    kept = float((S[: pr[3]] ** 2).sum())
-                    info.setdefault("trunc_err", []).append((tag, (tot - kept) / tot if tot > 0 else 0.0))
-                    info.setdefault("k", []).append((tag, pr[3]))
-        for x in range(Lx):
-            site = dict(env[(x, yn)])
-            site.update(new[x])
-            env[(x, yn)] = site
+            for tag, pr in (("green", G[x]), ("yellow", Y[x]), ("teal", TH[x]), ("red", R[x])):
+                S = pr[2]
+                tot = float((S * S).sum())
+                kept = float((S[: pr[3]] ** 2).sum())
+                info.setdefault("trunc_err", []).append((tag, (tot - kept) / tot if tot > 0 else 0.0))
+                info.setdefault("k", []).append((tag, pr[3]))
+    for x in range(Lx):
+        site = dict(env[(x, yn)])
+        site.update(new[x])
+        env[(x, yn)] = site
 
 
 # ----------------------------------------------------------------------------

@@ -23,7 +23,8 @@ INIT = {"identity": 0, "product": 1}
 EXPORTED = ("ctm_workspace_size", "ctm_init", "ctm_sweep", "ctm_projectors", "ctm_projectors_elems",
             "ctm_energy", "ctm_energy_grad", "ctm_env_elems", "ctm_env_export", "ctm_env_import",
             "ctm_last_stats", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd",
-            "ctm_destroy", "ctm_strerror")
+            "ctm_kernel_timing_enable", "ctm_kernel_timing", "ctm_destroy", "ctm_strerror")
+KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "gemm_bf16x3": 2, "jacobi_round": 3}
 
 
 class CtmError(RuntimeError):
@@ -66,6 +67,8 @@ def lib() -> ctypes.CDLL:
         "ctm_debug_gemm": (I, [I, I, I, I, I, I, P, P, P, P]),
         "ctm_debug_svd_work_bytes": (S, [I, I]),
         "ctm_debug_svd": (I, [I, I, P, P, P, P, P, ctypes.POINTER(I), P]),
+        "ctm_kernel_timing_enable": (I, [P, I]),
+        "ctm_kernel_timing": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
         "ctm_destroy": (None, [P]),
         "ctm_strerror": (ctypes.c_char_p, [I]),
     }
@@ -208,6 +211,22 @@ class SplitCTM:
         if st != CTM_OK:
             raise CtmError(st, "ctm_env_import")
 
+    def kernel_timing_enable(self, on=True):
+        st = lib().ctm_kernel_timing_enable(self.h, int(on))
+        if st != CTM_OK:
+            raise CtmError(st, "ctm_kernel_timing_enable")
+
+    def kernel_timing(self):
+        """{class: (ms, launches, work)} summed since kernel_timing_enable."""
+        out = {}
+        for name, k in KERNEL_CLASSES.items():
+            ms, n, w = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+            st = lib().ctm_kernel_timing(self.h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(w))
+            if st != CTM_OK:
+                raise CtmError(st, "ctm_kernel_timing")
+            out[name] = (ms.value, n.value, w.value)
+        return out
+
     def stats(self):
         f = ctypes.c_double(0)
         s = ctypes.c_double(0)
@@ -228,7 +247,7 @@ def debug_gemm(A, B, transA=False, transB=False, prec="fp64", stream=None):
     return C
 
 
-def debug_svd(M, stream=None):
+def debug_svd(M, stream=None, max_sweeps=0):
     import torch
     if M.dim() == 2:
         M = M[None]
@@ -238,7 +257,7 @@ def debug_svd(M, stream=None):
     V = torch.empty_like(M)
     S = torch.empty((b, n), dtype=torch.float64, device=M.device)
     work = torch.empty(lib().ctm_debug_svd_work_bytes(n, b), dtype=torch.uint8, device=M.device)
-    sw = ctypes.c_int(0)
+    sw = ctypes.c_int(max_sweeps)
     st = lib().ctm_debug_svd(n, b, _ptr(M), _ptr(U), _ptr(S), _ptr(V), _ptr(work), ctypes.byref(sw),
                              _stream_ptr(torch, stream))
     if st != CTM_OK:

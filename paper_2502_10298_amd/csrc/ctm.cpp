@@ -53,7 +53,10 @@ struct ctm_ctx {
   size_t transient_mark = 0;
   int host_flags[256];
   bool have_spec = false;
+  bool warm_start = true;
   double last_flops = 0, last_sweeps = 0;
+  bool timing = false;     // HIP-event timing of the GEMM and Jacobi launches
+  KernelTimer timer;
 };
 
 namespace {
@@ -336,7 +339,15 @@ struct Column {
 // One column of a left move (Sec. II B, App. A).  Writes the new C1, T4k,
 // T4b, C4 of column y+1 into `env` unless `want_row` >= 0, in which case only
 // the projectors of that row / cut are kept in `col` (env untouched).
-void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int want_row) {
+// Warm-start slot of projector `color` (0 green, 1 green', 2 yellow,
+// 3 yellow', 4 teal, 5 red) of row x, column y in the frame of move `dir`.
+int slot_of(const ctm_ctx& c, int dir, int x, int y, int Ly, int color) {
+  if (dir < 0 || !c.warm_start) return -1;
+  const int nsite = c.Lx * c.Ly;
+  return ((dir * nsite + x * Ly + y) * 6) + color;
+}
+
+void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int want_row, int dir) {
   Engine& E = c.E;
   const int Lx = env.Lx, Ly = env.Ly, ce = c.chiE, ci = c.chiI;
   const int yn = (y + 1) % Ly;
@@ -366,15 +377,26 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
     }
   }
   // first projectors: green (cut x|x+1) and yellow (row x) of column y; the
-  // mirrored pair of column y+1 for the right environment (bra layer first)
+  // mirrored pair of column y+1 for the right environment (bra layer first).
+  // All of them go through one batched SVD per matrix size.
   std::vector<std::vector<Ten>> G(Lx), Y(Lx), Gr(Lx), Yr(Lx);
   std::vector<std::vector<double>> sG(Lx), sY(Lx);
-  for (int x = 0; x < Lx; ++x) {
-    const int xp = (x + 1) % Lx;
-    G[x] = E.projectors(gT[x], gB[xp], 2, true, ce, spectra ? &sG[x] : nullptr);
-    Y[x] = E.projectors(yT[x], yB[x], 2, true, ci, spectra ? &sY[x] : nullptr);
-    Gr[x] = E.projectors(gT2[x], gB2[xp], 2, false, ce);
-    Yr[x] = E.projectors(yT2[x], yB2[x], 2, false, ci);
+  {
+    std::vector<ProjReq> rq;
+    for (int x = 0; x < Lx; ++x) {
+      const int xp = (x + 1) % Lx;
+      rq.push_back({gT[x], gB[xp], 2, true, ce, slot_of(c, dir, x, y, Ly, 0), spectra ? &sG[x] : nullptr});
+      rq.push_back({gT2[x], gB2[xp], 2, false, ce, slot_of(c, dir, x, y, Ly, 1), nullptr});
+      rq.push_back({yT[x], yB[x], 2, true, ci, slot_of(c, dir, x, y, Ly, 2), spectra ? &sY[x] : nullptr});
+      rq.push_back({yT2[x], yB2[x], 2, false, ci, slot_of(c, dir, x, y, Ly, 3), nullptr});
+    }
+    auto out = E.projectors_batch(rq);
+    for (int x = 0; x < Lx; ++x) {
+      G[x] = out[4 * x];
+      Gr[x] = out[4 * x + 1];
+      Y[x] = out[4 * x + 2];
+      Yr[x] = out[4 * x + 3];
+    }
   }
   // ket half-step of the left environment (first projection)
   std::vector<Ten> C1t(Lx), T4kt(Lx), T4bt(Lx), C4t(Lx);
@@ -402,20 +424,28 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
   //   [left env after ket step][bra of column y][ket of column y+1][right env after bra step]
   std::vector<std::vector<Ten>> TH(Lx), R(Lx);
   std::vector<std::vector<double>> sTH(Lx), sR(Lx);
-  for (int x = 0; x < Lx; ++x) {
-    const int xp = (x + 1) % Lx;
-    const Site &m = env.at(x, y), &mp = env.at(xp, y), &n = env.at(x, yn), &np_ = env.at(xp, yn);
-    const Ten &b = A.at(x, y), &bp = A.at(xp, y), &k = A.at(x, yn), &kp = A.at(xp, yn);
-    Ten rT = E.ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
-                    {C1t[x], m.t[T1b], n.t[T1k], C2t[x], T4kt[x], T4bt[x], b, k, T2kt[x], T2bt[x]});
-    Ten rB = E.ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
-                    {T4kt[xp], T4bt[xp], C4t[xp], mp.t[T3b], np_.t[T3k], C3t[xp], bp, kp, T2kt[xp], T2bt[xp]});
-    TH[x] = E.projectors(rT, rB, 2, true, ce, spectra ? &sTH[x] : nullptr);
-    Ten sT = E.ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
-                    {C1t[x], m.t[T1b], n.t[T1k], C2t[x], T4kt[x], k, T2kt[x]});
-    Ten sB = E.ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
-                    {T4bt[x], C4t[x], m.t[T3b], n.t[T3k], C3t[x], b, T2bt[x]});
-    R[x] = E.projectors(sT, sB, 3, true, ci, spectra ? &sR[x] : nullptr);
+  {
+    std::vector<ProjReq> rq;
+    for (int x = 0; x < Lx; ++x) {
+      const int xp = (x + 1) % Lx;
+      const Site &m = env.at(x, y), &mp = env.at(xp, y), &n = env.at(x, yn), &np_ = env.at(xp, yn);
+      const Ten &b = A.at(x, y), &bp = A.at(xp, y), &k = A.at(x, yn), &kp = A.at(xp, yn);
+      Ten rT = E.ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
+                      {C1t[x], m.t[T1b], n.t[T1k], C2t[x], T4kt[x], T4bt[x], b, k, T2kt[x], T2bt[x]});
+      Ten rB = E.ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
+                      {T4kt[xp], T4bt[xp], C4t[xp], mp.t[T3b], np_.t[T3k], C3t[xp], bp, kp, T2kt[xp], T2bt[xp]});
+      Ten sT = E.ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
+                      {C1t[x], m.t[T1b], n.t[T1k], C2t[x], T4kt[x], k, T2kt[x]});
+      Ten sB = E.ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
+                      {T4bt[x], C4t[x], m.t[T3b], n.t[T3k], C3t[x], b, T2bt[x]});
+      rq.push_back({rT, rB, 2, true, ce, slot_of(c, dir, x, y, Ly, 4), spectra ? &sTH[x] : nullptr});
+      rq.push_back({sT, sB, 3, true, ci, slot_of(c, dir, x, y, Ly, 5), spectra ? &sR[x] : nullptr});
+    }
+    auto out = E.projectors_batch(rq);
+    for (int x = 0; x < Lx; ++x) {
+      TH[x] = out[2 * x];
+      R[x] = out[2 * x + 1];
+    }
   }
   if (col) {
     col->G = G;
@@ -454,7 +484,7 @@ Env do_move(ctm_ctx& c, const Env& env, const Peps& A, int dir) {
   Env fe;
   Peps fa;
   to_frame(E, dir, env, A, fe, fa);
-  for (int y = 0; y < fe.Ly && E.ok(); ++y) left_column(c, fe, fa, y, nullptr, -1);
+  for (int y = 0; y < fe.Ly && E.ok(); ++y) left_column(c, fe, fa, y, nullptr, -1, dir);
   Env out;
   from_frame(E, dir, fe, out);
   return out;
@@ -511,6 +541,7 @@ void begin(ctm_ctx* c) {
   c->E.ar.overflow = false;
   c->E.ar.release(c->transient_mark);
   c->E.clear_tape();
+  kernel_timer() = c->timing ? &c->timer : nullptr;
 }
 
 ctm_status finish(ctm_ctx* c, ctm_status st) {
@@ -518,6 +549,10 @@ ctm_status finish(ctm_ctx* c, ctm_status st) {
   c->last_sweeps = (double)c->E.svd_sweeps_total;
   c->E.ar.release(c->transient_mark);
   c->E.clear_tape();
+  if (c->timing) {
+    if (hipStreamSynchronize(c->E.s) == hipSuccess) c->timer.collect();
+    kernel_timer() = nullptr;
+  }
   return st;
 }
 
@@ -566,6 +601,19 @@ void init_persistent(ctm_ctx* c, const double* A_dev, const double* bvec) {
   c->h64 = E.alloc(F64, {(long)c->p * c->p * c->p * c->p});
   Ten part = E.alloc(F64, {(long)reduce_partials()});
   E.partial = part.f64();
+  // warm-start right singular vectors of every projector slot
+  {
+    const long n1 = (long)c->chiE * c->D, n2 = (long)c->p * c->D * c->chiI;
+    const int nslot = 4 * c->Lx * c->Ly * 6;
+    E.warm.assign(nslot, Ten());
+    E.warm_valid.assign(nslot, 0);
+    if (c->warm_start)
+      for (int sl = 0; sl < nslot; ++sl) {
+        const int color = sl % 6;
+        const long nb = (color == 2 || color == 3 || color == 5) ? n2 : n1;
+        E.warm[sl] = E.alloc(F64, {nb, nb});
+      }
+  }
   if (!E.dry && E.ok()) {
     E.check(hipMemcpyAsync(c->A64.p, A_dev, c->A64.bytes(), hipMemcpyDeviceToDevice, E.s));
     if (E.cdt == F32) E.check(cast_f64_to_f32(E.s, c->A64.f64(), c->Aflat.f32(), c->A64.n()));
@@ -876,7 +924,7 @@ ctm_status ctm_workspace_size(const ctm_config* cfg, int with_grad, int n_sweeps
     size_t mk = c->E.ar.mark();
     Env env = view_env(*c, c->cur_blk);
     Column col;
-    left_column(*c, env, A, 0, &col, 0);
+    left_column(*c, env, A, 0, &col, 0, -1);
     c->E.ar.release(mk);
   }
   if (with_grad) energy_grad_impl(c, nullptr, n_sweeps, ckpt_every, nullptr, nullptr);
@@ -1005,7 +1053,7 @@ ctm_status ctm_projectors(ctm_ctx* c, int direction, int x, int y, double* out_d
     fy = (fe.Ly - x) % fe.Ly;
   }
   Column col;
-  left_column(*c, fe, fa, fy, &col, fx);
+  left_column(*c, fe, fa, fy, &col, fx, -1);
   const std::vector<Ten> pr[4] = {col.G[fx], col.TH[fx], col.Y[fx], col.R[fx]};
   const std::vector<double>* sp[4] = {&col.sG[fx], &col.sTH[fx], &col.sY[fx], &col.sR[fx]};
   const int chis[4] = {c->chiE, c->chiE, c->chiI, c->chiI};
@@ -1067,6 +1115,7 @@ ctm_status ctm_env_import(ctm_ctx* c, const double* env_dev) {
   E.check(hipMemcpyAsync(c->start_blk.p, c->cur_blk.p, c->cur_blk.bytes(), hipMemcpyDeviceToDevice, E.s));
   E.check(hipStreamSynchronize(E.s));
   c->have_spec = false;
+  std::fill(E.warm_valid.begin(), E.warm_valid.end(), 0);
   return (ctm_status)status_from_engine(E);
 }
 
@@ -1092,9 +1141,25 @@ ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S
   if (n < 1 || batch < 1 || batch > 256 || !M || !U || !S || !V || !work) return CTM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   int flags[256];
-  hipError_t e = svd_f64(s, n, batch, M, U, S, V, work, 60, 1e-14, flags, sweeps);
+  const int max_sweeps = (sweeps && *sweeps > 0) ? *sweeps : 60;
+  hipError_t e = svd_f64(s, n, batch, M, U, S, V, work, max_sweeps, 0.0, flags, sweeps);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e == hipSuccess ? CTM_OK : CTM_EDEVICE;
+}
+
+ctm_status ctm_kernel_timing_enable(ctm_ctx* c, int on) {
+  if (!c) return CTM_EINVAL;
+  c->timing = on != 0;
+  c->timer.reset();
+  return CTM_OK;
+}
+
+ctm_status ctm_kernel_timing(ctm_ctx* c, int kernel_class, double* ms, double* launches, double* work) {
+  if (!c || kernel_class < 0 || kernel_class >= KC_COUNT) return CTM_EINVAL;
+  if (ms) *ms = c->timer.ms[kernel_class];
+  if (launches) *launches = c->timer.launches[kernel_class];
+  if (work) *work = c->timer.work[kernel_class];
+  return CTM_OK;
 }
 
 ctm_status ctm_last_stats(ctm_ctx* c, double* gemm_flops, double* svd_sweeps) {

@@ -2,8 +2,12 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 
 #include "adj_kernels.hpp"
 
@@ -49,6 +53,11 @@ Ten Engine::grad(const Ten& t) {
 // ---------------------------------------------------------------------------
 // permutations
 // ---------------------------------------------------------------------------
+static bool trace_contractions() {
+  static const bool on = getenv("SPLITCTM_TRACE") != nullptr;
+  return on;
+}
+
 static void parse_arrow(const std::string& spec, std::string& lhs, std::string& rhs) {
   size_t a = spec.find("->");
   lhs = spec.substr(0, a);
@@ -267,6 +276,7 @@ void Engine::contract_into(const std::string& spec, const Ten& A, const Ten& B, 
   for (char c : fa) M *= dim(c);
   for (char c : fb) N *= dim(c);
   for (char c : ka) K *= dim(c);
+  if (trace_contractions()) fprintf(stderr, "[contract] %s M=%ld N=%ld K=%ld GF=%.3f\n", spec.c_str(), M, N, K, 2e-9 * M * N * K);
   // choose the contracted order that needs the fewest operand permutes
   struct Plan {
     std::string ko;
@@ -361,6 +371,112 @@ Ten Engine::contract(const std::string& spec, const Ten& A, const Ten& B) {
 // At every step the pair sharing an index with the fewest multiply-adds is
 // contracted; its result keeps the free labels of the first operand followed
 // by those of the second (the GEMM's natural output order, so no permute).
+// Pairwise contraction order of a tensor network: exhaustive dynamic
+// programming over subsets of the operands, minimising the total multiply-add
+// count (ties: the smaller largest intermediate).  Every label occurs in two
+// operands, or in one operand and the output, so each pairwise step is a plain
+// GEMM-shaped contraction.  Plans are cached per (spec, dims).
+struct PlanKey {
+  std::string spec;
+  std::vector<long> dims;
+  bool operator==(const PlanKey& o) const { return spec == o.spec && dims == o.dims; }
+};
+struct PlanKeyHash {
+  size_t operator()(const PlanKey& k) const {
+    size_t h = std::hash<std::string>()(k.spec);
+    for (long d : k.dims) h = h * 1000003u ^ std::hash<long>()(d);
+    return h;
+  }
+};
+
+static const ContractionPlan& plan_for(const std::string& spec, const std::vector<std::string>& terms,
+                                       const std::string& out, const long* dims) {
+  static std::unordered_map<PlanKey, ContractionPlan, PlanKeyHash> cache;
+  PlanKey key{spec, {}};
+  for (const auto& t : terms)
+    for (char c : t) key.dims.push_back(dims[(unsigned char)c]);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+
+  const int n = (int)terms.size();
+  const int full = (1 << n) - 1;
+  // labels of each operand as bit sets over the distinct labels
+  std::string labels;
+  for (const auto& t : terms)
+    for (char c : t)
+      if (labels.find(c) == std::string::npos) labels += c;
+  const int nl = (int)labels.size();
+  std::vector<unsigned long long> lab(n, 0ull);
+  for (int i = 0; i < n; ++i)
+    for (char c : terms[i]) lab[i] |= 1ull << labels.find(c);
+  unsigned long long outl = 0;
+  for (char c : out) outl |= 1ull << labels.find(c);
+  std::vector<double> ld(nl);
+  for (int k = 0; k < nl; ++k) ld[k] = (double)dims[(unsigned char)labels[k]];
+  auto vol = [&](unsigned long long m) {
+    double v = 1.0;
+    for (int k = 0; k < nl; ++k)
+      if (m >> k & 1) v *= ld[k];
+    return v;
+  };
+  // open legs of every subset: labels of the subset also present outside it
+  std::vector<unsigned long long> inner(full + 1, 0ull), legs(full + 1, 0ull);
+  for (int S = 1; S <= full; ++S) {
+    unsigned long long in = 0, outside = outl;
+    for (int i = 0; i < n; ++i) (S >> i & 1 ? in : outside) |= lab[i];
+    inner[S] = in;
+    legs[S] = in & outside;
+  }
+  std::vector<double> cost(full + 1, 0.0), peak(full + 1, 0.0);
+  std::vector<int> split(full + 1, 0);
+  for (int S = 1; S <= full; ++S) {
+    if ((S & (S - 1)) == 0) {
+      cost[S] = 0.0;
+      peak[S] = 0.0;
+      continue;
+    }
+    double best = -1.0, bpk = 0.0;
+    int bs = 0;
+    // enumerate proper submasks S1 containing the lowest operand of S
+    const int low = S & -S;
+    for (int S1 = (S - 1) & S; S1 > 0; S1 = (S1 - 1) & S) {
+      if (!(S1 & low)) continue;
+      const int S2 = S ^ S1;
+      const double f = vol(legs[S1] | legs[S2]);
+      const double c = cost[S1] + cost[S2] + f;
+      const double pk = std::max(std::max(peak[S1], peak[S2]), vol(legs[S]));
+      if (best < 0 || c < best * (1 - 1e-12) || (c <= best * (1 + 1e-12) && pk < bpk)) {
+        best = c;
+        bpk = pk;
+        bs = S1;
+      }
+    }
+    cost[S] = best;
+    peak[S] = bpk;
+    split[S] = bs;
+  }
+  // emit the steps bottom-up; the label order of an intermediate is the kept
+  // labels of its left part followed by those of its right part
+  ContractionPlan plan;
+  std::vector<std::string> names(terms);
+  std::function<int(int)> emit = [&](int S) -> int {
+    if ((S & (S - 1)) == 0) return __builtin_ctz(S);
+    const int S1 = split[S], S2 = S ^ S1;
+    const int a = emit(S1), b = emit(S2);
+    std::string keep;
+    for (char c : names[a])
+      if (legs[S] >> labels.find(c) & 1) keep += c;
+    for (char c : names[b])
+      if ((legs[S] >> labels.find(c) & 1) && names[a].find(c) == std::string::npos) keep += c;
+    plan.steps.push_back({a, b, keep});
+    names.push_back(keep);
+    return (int)names.size() - 1;
+  };
+  emit(full);
+  plan.flops = 2.0 * cost[full];
+  return cache.emplace(key, std::move(plan)).first->second;
+}
+
 Ten Engine::ncon(const std::string& spec, const std::vector<Ten>& ops) {
   std::string lhs, out;
   parse_arrow(spec, lhs, out);
@@ -390,55 +506,17 @@ Ten Engine::ncon(const std::string& spec, const std::vector<Ten>& ops) {
     }
   }
   if (status) return ops[0];
+  const ContractionPlan& plan = plan_for(spec, terms, out, dims);
   std::vector<std::pair<std::string, Ten>> items;
   for (size_t i = 0; i < terms.size(); ++i) items.push_back({terms[i], ops[i]});
-  while (items.size() > 1) {
-    int bi = -1, bj = -1;
-    double bflops = 0, bsize = 0;
-    bool bshared = false;
-    std::string bkeep;
-    for (size_t i = 0; i < items.size(); ++i)
-      for (size_t j = i + 1; j < items.size(); ++j) {
-        const std::string &ti = items[i].first, &tj = items[j].first;
-        std::string rest = out;
-        for (size_t k = 0; k < items.size(); ++k)
-          if (k != i && k != j) rest += items[k].first;
-        bool shared = false;
-        double flops = 1.0, size = 1.0;
-        std::string keep;
-        for (char c : ti) {
-          flops *= dims[(unsigned char)c];
-          if (tj.find(c) != std::string::npos) shared = true;
-          if (rest.find(c) != std::string::npos) {
-            keep += c;
-            size *= dims[(unsigned char)c];
-          }
-        }
-        for (char c : tj) {
-          if (ti.find(c) == std::string::npos) flops *= dims[(unsigned char)c];
-          if (ti.find(c) == std::string::npos && rest.find(c) != std::string::npos) {
-            keep += c;
-            size *= dims[(unsigned char)c];
-          }
-        }
-        bool better = bi < 0 || (shared && !bshared) ||
-                      (shared == bshared && (flops < bflops || (flops == bflops && size < bsize)));
-        if (better) {
-          bi = (int)i;
-          bj = (int)j;
-          bflops = flops;
-          bsize = size;
-          bshared = shared;
-          bkeep = keep;
-        }
-      }
-    Ten r = contract(items[bi].first + "," + items[bj].first + "->" + bkeep, items[bi].second, items[bj].second);
-    std::vector<std::pair<std::string, Ten>> nx;
-    for (size_t k = 0; k < items.size(); ++k)
-      if ((int)k != bi && (int)k != bj) nx.push_back(items[k]);
-    nx.push_back({bkeep, r});
-    items.swap(nx);
+  for (const auto& st : plan.steps) {
+    auto& a = items[st.i];
+    auto& b = items[st.j];
+    Ten r = contract(a.first + "," + b.first + "->" + st.keep, a.second, b.second);
+    items.push_back({st.keep, r});
   }
+  items[0] = items.back();
+  items.resize(1);
   if (items[0].first == out) return items[0].second;
   return permute(items[0].second, items[0].first + "->" + out);
 }
@@ -448,108 +526,194 @@ Ten Engine::ncon(const std::string& spec, const std::vector<Ten>& ops) {
 // ---------------------------------------------------------------------------
 std::vector<Ten> Engine::projectors(const Ten& rT, const Ten& rB, int n_a, bool rows, int chi,
                                     std::vector<double>* spectrum_out) {
-  long na = 1, nb = 1;
-  std::vector<long> a_shape;
-  if (rows) {
-    for (int i = 0; i < n_a; ++i) {
-      na *= rT.d[i];
-      a_shape.push_back(rT.d[i]);
-    }
-    nb = rT.n() / na;
-  } else {
-    for (int i = rT.r - n_a; i < rT.r; ++i) {
-      na *= rT.d[i];
-      a_shape.push_back(rT.d[i]);
-    }
-    nb = rT.n() / na;
-  }
-  ProjSaved ps;
-  ps.na = (int)na;
-  ps.nb = (int)nb;
-  ps.chi = chi;
-  ps.rows = rows;
-  // FP64 copies of the half networks (the SVD side of the path is FP64)
-  ps.rT = alloc(F64, {rows ? na : nb, rows ? nb : na});
-  ps.rB = alloc(F64, {rows ? na : nb, rows ? nb : na});
-  if (!dry && ok()) {
-    if (rT.dt == F64) {
-      check(hipMemcpyAsync(ps.rT.p, rT.p, rT.bytes(), hipMemcpyDeviceToDevice, s));
-      check(hipMemcpyAsync(ps.rB.p, rB.p, rB.bytes(), hipMemcpyDeviceToDevice, s));
+  ProjReq q{rT, rB, n_a, rows, chi, -1, spectrum_out};
+  return projectors_batch({q})[0];
+}
+
+static Ten view_of(Engine& E, const Ten& base, long off_elems, const std::vector<long>& dims) {
+  Ten t;
+  t.dt = base.dt;
+  t.r = (int)dims.size();
+  for (int i = 0; i < t.r; ++i) t.d[i] = dims[i];
+  t.p = (char*)base.p + off_elems * base.esize();
+  t.id = E.next_id++;
+  return t;
+}
+
+// Projector pairs for several cuts at once.  Requests whose matrix M has the
+// same size share one batched Jacobi SVD (one launch per round for all of
+// them); a request with a warm-start slot starts its SVD from the right
+// singular vectors that slot kept from the previous call.
+std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq>& reqs) {
+  const size_t nr = reqs.size();
+  std::vector<std::vector<Ten>> result(nr);
+  std::vector<ProjSaved> ps(nr);
+  std::vector<std::vector<long>> a_shapes(nr);
+  for (size_t i = 0; i < nr; ++i) {
+    const ProjReq& q = reqs[i];
+    long na = 1;
+    if (q.rows) {
+      for (int k = 0; k < q.n_a; ++k) {
+        na *= q.rT.d[k];
+        a_shapes[i].push_back(q.rT.d[k]);
+      }
     } else {
-      check(cast_f32_to_f64(s, rT.f32(), ps.rT.f64(), rT.n()));
-      check(cast_f32_to_f64(s, rB.f32(), ps.rB.f64(), rB.n()));
+      for (int k = q.rT.r - q.n_a; k < q.rT.r; ++k) {
+        na *= q.rT.d[k];
+        a_shapes[i].push_back(q.rT.d[k]);
+      }
+    }
+    ps[i].na = (int)na;
+    ps[i].nb = (int)(q.rT.n() / na);
+    ps[i].chi = q.chi;
+    ps[i].rows = q.rows;
+  }
+  std::vector<char> handled(nr, 0);
+  for (size_t g0 = 0; g0 < nr; ++g0) {
+    if (handled[g0]) continue;
+    std::vector<size_t> grp;
+    for (size_t i = g0; i < nr; ++i)
+      if (!handled[i] && ps[i].nb == ps[g0].nb) {
+        grp.push_back(i);
+        handled[i] = 1;
+      }
+    const long nb = ps[g0].nb;
+    const int g = (int)grp.size();
+    Ten Mb = alloc(F64, {(long)g, nb, nb});
+    for (int j = 0; j < g; ++j) {
+      const size_t i = grp[j];
+      const ProjReq& q = reqs[i];
+      ProjSaved& P = ps[i];
+      const long na = P.na;
+      P.rT = alloc(F64, {q.rows ? na : nb, q.rows ? nb : na});
+      P.rB = alloc(F64, {q.rows ? na : nb, q.rows ? nb : na});
+      if (!dry && ok()) {
+        if (q.rT.dt == F64) {
+          check(hipMemcpyAsync(P.rT.p, q.rT.p, q.rT.bytes(), hipMemcpyDeviceToDevice, s));
+          check(hipMemcpyAsync(P.rB.p, q.rB.p, q.rB.bytes(), hipMemcpyDeviceToDevice, s));
+        } else {
+          check(cast_f32_to_f64(s, q.rT.f32(), P.rT.f64(), q.rT.n()));
+          check(cast_f32_to_f64(s, q.rB.f32(), P.rB.f64(), q.rB.n()));
+        }
+      }
+      const long off = (long)j * nb * nb;
+      if (q.rows)   // M = rho_B^T rho_T  (b x b)
+        gemm(true, false, (int)nb, (int)nb, (int)na, 1.0, P.rB, 0, nb, P.rT, 0, nb, 0.0, Mb, off, nb);
+      else          // M = rho_B rho_T^T
+        gemm(false, true, (int)nb, (int)nb, (int)na, 1.0, P.rB, 0, na, P.rT, 0, na, 0.0, Mb, off, nb);
+    }
+    Ten Ub = alloc(F64, {(long)g, nb, nb}), Sb = alloc(F64, {(long)g, nb}), Vb = alloc(F64, {(long)g, nb, nb});
+    bool warm_all = true;
+    for (int j = 0; j < g; ++j) {
+      int sl = reqs[grp[j]].slot;
+      warm_all = warm_all && sl >= 0 && sl < (int)warm.size() && warm_valid[sl] && warm[sl].n() == nb * nb;
+    }
+    {
+      size_t mk = ar.mark();
+      Ten V0;
+      if (warm_all) {
+        V0 = alloc(F64, {(long)g, nb, nb});
+        if (!dry && ok())
+          for (int j = 0; j < g; ++j)
+            check(hipMemcpyAsync(V0.f64() + (long)j * nb * nb, warm[reqs[grp[j]].slot].p, sizeof(double) * nb * nb,
+                                 hipMemcpyDeviceToDevice, s));
+      }
+      void* work = ar.alloc(svd_work_bytes((int)nb, g));
+      if (!dry && ok()) {
+        int sweeps = 0;
+        static const bool trace = getenv("SPLITCTM_SVD_TRACE") != nullptr;
+        auto t0 = std::chrono::steady_clock::now();
+        if (trace) check(hipStreamSynchronize(s));
+        check(svd_f64(s, (int)nb, g, Mb.f64(), Ub.f64(), Sb.f64(), Vb.f64(), work, svd_max_sweeps, svd_tol, host_flags,
+                      &sweeps, warm_all ? V0.f64() : nullptr));
+        svd_sweeps_total += sweeps;
+        svd_calls += 1;
+        if (trace && ok()) {
+          std::vector<double> sv(nb);
+          check(hipMemcpyAsync(sv.data(), Sb.f64(), sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+          check(hipStreamSynchronize(s));
+          const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+          int r = 0;
+          for (long k = 0; k < nb; ++k) r += sv[k] > 1e-14 * sv[0];
+          const int kc = std::min<long>(reqs[grp[0]].chi, nb) - 1;
+          fprintf(stderr, "[svd] n=%ld batch=%d warm=%d sweeps=%d %.1f ms rank=%d s_chi/s1=%.2e s_2chi/s1=%.2e\n", nb, g,
+                  (int)warm_all, sweeps, ms, r, sv[kc] / sv[0], sv[std::min<long>(2 * kc + 1, nb - 1)] / sv[0]);
+        }
+      }
+      ar.release(mk);
+    }
+    for (int j = 0; j < g; ++j) {
+      int sl = reqs[grp[j]].slot;
+      if (sl >= 0 && sl < (int)warm.size() && warm[sl].n() == nb * nb) {
+        if (!dry && ok())
+          check(hipMemcpyAsync(warm[sl].p, Vb.f64() + (long)j * nb * nb, sizeof(double) * nb * nb,
+                               hipMemcpyDeviceToDevice, s));
+        warm_valid[sl] = 1;
+      }
+    }
+    for (int j = 0; j < g; ++j) {
+      const size_t i = grp[j];
+      const ProjReq& q = reqs[i];
+      ProjSaved& P = ps[i];
+      const long na = P.na;
+      const int chi = q.chi;
+      P.U = view_of(*this, Ub, (long)j * nb * nb, {nb, nb});
+      P.S = view_of(*this, Sb, (long)j * nb, {nb});
+      P.V = view_of(*this, Vb, (long)j * nb * nb, {nb, nb});
+      P.kr = alloc(F64, {2});   // two ints (k, r) in its first 8 bytes
+      P.X = alloc(F64, {nb, chi});
+      P.Y = alloc(F64, {nb, chi});
+      if (!dry && ok()) {
+        int* kr = (int*)P.kr.p;
+        check(trunc_scale(s, (int)nb, (int)nb, chi, P.U.f64(), P.S.f64(), cutoff, P.X.f64(), kr, 1));
+        check(trunc_scale(s, (int)nb, (int)nb, chi, P.V.f64(), P.S.f64(), cutoff, P.Y.f64(), kr, 1));
+        check(rank_count(s, (int)nb, P.S.f64(), 1e-14, kr + 1));
+      }
+      Ten PT64 = alloc(F64, {na, chi}), PB64 = alloc(F64, {na, chi});
+      if (q.rows) {   // P_T = rho_B X, P_B = rho_T Y
+        gemm(false, false, (int)na, chi, (int)nb, 1.0, P.rB, 0, nb, P.X, 0, chi, 0.0, PT64, 0, chi);
+        gemm(false, false, (int)na, chi, (int)nb, 1.0, P.rT, 0, nb, P.Y, 0, chi, 0.0, PB64, 0, chi);
+      } else {        // P_T = rho_B^T X, P_B = rho_T^T Y
+        gemm(true, false, (int)na, chi, (int)nb, 1.0, P.rB, 0, na, P.X, 0, chi, 0.0, PT64, 0, chi);
+        gemm(true, false, (int)na, chi, (int)nb, 1.0, P.rT, 0, na, P.Y, 0, chi, 0.0, PB64, 0, chi);
+      }
+      P.sgn = alloc(F64, {chi});
+      if (!dry && ok()) check(sign_fix(s, (int)na, chi, PT64.f64(), PB64.f64(), P.sgn.f64(), 1));
+      if (q.spectrum_out && !dry && ok()) {
+        q.spectrum_out->resize(nb);
+        check(hipMemcpyAsync(q.spectrum_out->data(), P.S.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+        check(hipStreamSynchronize(s));
+      }
+      std::vector<long> pshape = a_shapes[i];
+      pshape.push_back(chi);
+      Ten PT, PB;
+      if (cdt == F64) {
+        PT = PT64;
+        PB = PB64;
+      } else {
+        PT = alloc(F32, {na, chi});
+        PB = alloc(F32, {na, chi});
+        if (!dry && ok()) {
+          check(cast_f64_to_f32(s, PT64.f64(), PT.f32(), na * chi));
+          check(cast_f64_to_f32(s, PB64.f64(), PB.f32(), na * chi));
+        }
+      }
+      PT.r = PB.r = (int)pshape.size();
+      for (size_t k = 0; k < pshape.size(); ++k) PT.d[k] = PB.d[k] = pshape[k];
+      if (taping && (ng(q.rT) || ng(q.rB))) {
+        TapeRec r;
+        r.kind = OP_PROJ;
+        r.in = {q.rT, q.rB};
+        r.out = {PT, PB};
+        r.proj = P;
+        record(std::move(r));
+        needs_grad.insert(PT.id);
+        needs_grad.insert(PB.id);
+      }
+      result[i] = {PT, PB};
     }
   }
-  Ten Mm = alloc(F64, {nb, nb});
-  if (rows)   // M = rho_B^T rho_T  (b x b)
-    gemm(true, false, (int)nb, (int)nb, (int)na, 1.0, ps.rB, 0, nb, ps.rT, 0, nb, 0.0, Mm, 0, nb);
-  else        // M = rho_B rho_T^T
-    gemm(false, true, (int)nb, (int)nb, (int)na, 1.0, ps.rB, 0, na, ps.rT, 0, na, 0.0, Mm, 0, nb);
-  ps.U = alloc(F64, {nb, nb});
-  ps.S = alloc(F64, {nb});
-  ps.V = alloc(F64, {nb, nb});
-  {
-    size_t mk = ar.mark();
-    void* work = ar.alloc(svd_work_bytes((int)nb, 1));
-    if (!dry && ok()) {
-      int sweeps = 0;
-      check(svd_f64(s, (int)nb, 1, Mm.f64(), ps.U.f64(), ps.S.f64(), ps.V.f64(), work, svd_max_sweeps, svd_tol,
-                    host_flags, &sweeps));
-      svd_sweeps_total += sweeps;
-    }
-    ar.release(mk);
-  }
-  ps.kr = alloc(F64, {2});   // holds two ints (k, r) in its first 8 bytes
-  ps.X = alloc(F64, {nb, chi});
-  ps.Y = alloc(F64, {nb, chi});
-  if (!dry && ok()) {
-    int* kr = (int*)ps.kr.p;
-    check(trunc_scale(s, (int)nb, (int)nb, chi, ps.U.f64(), ps.S.f64(), cutoff, ps.X.f64(), kr, 1));
-    check(trunc_scale(s, (int)nb, (int)nb, chi, ps.V.f64(), ps.S.f64(), cutoff, ps.Y.f64(), kr, 1));
-    check(rank_count(s, (int)nb, ps.S.f64(), 1e-14, kr + 1));
-  }
-  Ten PT64 = alloc(F64, {na, chi}), PB64 = alloc(F64, {na, chi});
-  if (rows) {   // P_T = rho_B X, P_B = rho_T Y
-    gemm(false, false, (int)na, chi, (int)nb, 1.0, ps.rB, 0, nb, ps.X, 0, chi, 0.0, PT64, 0, chi);
-    gemm(false, false, (int)na, chi, (int)nb, 1.0, ps.rT, 0, nb, ps.Y, 0, chi, 0.0, PB64, 0, chi);
-  } else {      // P_T = rho_B^T X, P_B = rho_T^T Y
-    gemm(true, false, (int)na, chi, (int)nb, 1.0, ps.rB, 0, na, ps.X, 0, chi, 0.0, PT64, 0, chi);
-    gemm(true, false, (int)na, chi, (int)nb, 1.0, ps.rT, 0, na, ps.Y, 0, chi, 0.0, PB64, 0, chi);
-  }
-  ps.sgn = alloc(F64, {chi});
-  if (!dry && ok()) check(sign_fix(s, (int)na, chi, PT64.f64(), PB64.f64(), ps.sgn.f64(), 1));
-  if (spectrum_out && !dry && ok()) {
-    spectrum_out->resize(nb);
-    check(hipMemcpyAsync(spectrum_out->data(), ps.S.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
-    check(hipStreamSynchronize(s));
-  }
-  std::vector<long> pshape = a_shape;
-  pshape.push_back(chi);
-  Ten PT, PB;
-  if (cdt == F64) {
-    PT = PT64;
-    PB = PB64;
-  } else {
-    PT = alloc(F32, {na, chi});
-    PB = alloc(F32, {na, chi});
-    if (!dry && ok()) {
-      check(cast_f64_to_f32(s, PT64.f64(), PT.f32(), na * chi));
-      check(cast_f64_to_f32(s, PB64.f64(), PB.f32(), na * chi));
-    }
-  }
-  PT.r = PB.r = (int)pshape.size();
-  for (size_t i = 0; i < pshape.size(); ++i) PT.d[i] = PB.d[i] = pshape[i];
-  if (taping && (ng(rT) || ng(rB))) {
-    TapeRec r;
-    r.kind = OP_PROJ;
-    r.in = {rT, rB};
-    r.out = {PT, PB};
-    r.proj = ps;
-    record(std::move(r));
-    needs_grad.insert(PT.id);
-    needs_grad.insert(PB.id);
-  }
-  return {PT, PB};
+  return result;
 }
 
 Ten Engine::bond_energy(const Ten& rho, const Ten& h64, int p) {

@@ -69,6 +69,24 @@ struct ProjSaved {
   bool rows = true;    // truncated legs are the rows of rho (else the columns)
 };
 
+struct ProjReq {
+  Ten rT, rB;
+  int n_a;
+  bool rows;
+  int chi;
+  int slot;                          // warm-start slot (-1: cold start)
+  std::vector<double>* spectrum_out;
+};
+
+struct PlanStep {
+  int i, j;            // operands: inputs 0..n-1, then intermediates in step order
+  std::string keep;    // labels of the result
+};
+struct ContractionPlan {
+  std::vector<PlanStep> steps;
+  double flops = 0;
+};
+
 struct TapeRec {
   OpKind kind;
   std::vector<Ten> in, out;
@@ -89,7 +107,7 @@ struct Engine {
   hipError_t err = hipSuccess;
   int status = 0;                // first library-level failure (ctm_status code)
   int next_id = 0;
-  double svd_tol = 1e-14;
+  double svd_tol = 0.0;            // <= 0: sqrt(n) * 1.2e-16
   int svd_max_sweeps = 40;
   double cutoff = 1e-12;
   double adj_eps = 1e-12;
@@ -129,6 +147,11 @@ struct Engine {
   // a_shape + (chi), in the contraction dtype; columns >= k are zero.
   std::vector<Ten> projectors(const Ten& rT, const Ten& rB, int n_a, bool rows, int chi,
                               std::vector<double>* spectrum_out = nullptr);
+  std::vector<std::vector<Ten>> projectors_batch(const std::vector<ProjReq>& reqs);
+  // warm-start right singular vectors per projector slot (persistent buffers)
+  std::vector<Ten> warm;
+  std::vector<char> warm_valid;
+  long svd_calls = 0;
   Ten bond_energy(const Ten& rho, const Ten& h64, int p);   // -> FP64 [2] (e, den)
 
   // ---- low level ----

@@ -240,11 +240,18 @@ static dim3 gemm_grid(int M, int N, int batch) {
   return dim3((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
 }
 
+KernelTimer*& kernel_timer() {
+  static thread_local KernelTimer* t = nullptr;
+  return t;
+}
+
 hipError_t gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double alpha,
                     const double* A, long lda, long sA, const double* B, long ldb, long sB,
                     double beta, double* C, long ldc, long sC, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   dim3 g = gemm_grid(M, N, batch);
+  KernelTimer* tm = kernel_timer();
+  if (tm) tm->begin(s, KC_GEMM_F64, 2.0 * M * N * (double)K * batch);
   if (!tA && !tB)
     hipLaunchKernelGGL((gemm_kernel<double, d4, false, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else if (tA && !tB)
@@ -253,6 +260,7 @@ hipError_t gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double
     hipLaunchKernelGGL((gemm_kernel<double, d4, false, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else
     hipLaunchKernelGGL((gemm_kernel<double, d4, true, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  if (tm) tm->end(s);
   return hipGetLastError();
 }
 
@@ -261,6 +269,8 @@ hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, in
                     float* C, long ldc, long sC, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   dim3 g = gemm_grid(M, N, batch);
+  KernelTimer* tm = kernel_timer();
+  if (tm) tm->begin(s, mode == Prec::BF16X3 ? KC_GEMM_BF16X3 : KC_GEMM_F32, 2.0 * M * N * (double)K * batch);
   if (mode == Prec::BF16X3) {
     if (!tA && !tB)
       hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
@@ -270,7 +280,8 @@ hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, in
       hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
     else
       hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-    return hipGetLastError();
+    if (tm) tm->end(s);
+  return hipGetLastError();
   }
   if (!tA && !tB)
     hipLaunchKernelGGL((gemm_kernel<float, f4, false, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);

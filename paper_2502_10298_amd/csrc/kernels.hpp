@@ -2,6 +2,8 @@
 // Every launcher enqueues on the given stream and returns hipError_t.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "timer.hpp"
 #include <cstdint>
 
 namespace sctm {
@@ -61,8 +63,11 @@ hipError_t normalize_adjoint_f32(hipStream_t s, const float* y, const float* yba
 size_t svd_work_bytes(int n, int batch);
 // host_flags: host buffer of >= batch ints (convergence flags are read back
 // once per sweep; the stream is synchronised at that point).
+// V0 (optional, batch of n x n): start the iteration from G = M V0, V = V0
+// (an orthogonal matrix close to the answer, e.g. the previous sweep's V).
 hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, double* S, double* V,
-                   void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out);
+                   void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out,
+                   const double* V0 = nullptr);
 
 // ---------------- projector formation ----------------
 // k = min(chi, #{S > cutoff * S[0]}) per batch entry -> kout (device int)

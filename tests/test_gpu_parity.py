@@ -58,9 +58,14 @@ def test_jacobi_svd(n, batch):
         rec = (U[i] * S[i]) @ V[i].T
         assert (rec - M[i]).norm() < 2e-12 * M[i].norm()
         assert torch.allclose(V[i].T @ V[i], torch.eye(n, dtype=torch.float64), atol=1e-12)
-        r = int((S[i] > 1e-13 * S[i][0]).sum())
+        # One-sided Jacobi with an absolute stopping rule fixes U = G / s column
+        # by column: U_j is orthogonal to working accuracy times s_1 / s_j, and
+        # U S (= M V) has a Gram matrix equal to diag(S^2) to eps * s_1^2.
+        US = U[i] * S[i]
+        assert torch.allclose(US.T @ US, torch.diag(S[i] ** 2), rtol=0, atol=1e-12 * float(S[i][0]) ** 2)
+        r = int((S[i] > 1e-4 * S[i][0]).sum())
         Ur = U[i][:, :r]
-        assert torch.allclose(Ur.T @ Ur, torch.eye(r, dtype=torch.float64), atol=1e-10)
+        assert torch.allclose(Ur.T @ Ur, torch.eye(r, dtype=torch.float64), atol=1e-8)
     assert sweeps < 60
 
 
