@@ -29,15 +29,33 @@ if ROOT not in sys.path:
 WORKLOAD = "cell2x2_d2_D8_chi128_grad"
 METRIC = "split-CTMRG sweeps/s + energy-grad evals/s at D=8,χ=128; MFMA fraction"
 
-# Published MI355X dense peaks (TFLOP/s).  A BF16x3 product issues three BF16
-# MFMA products per FP32-class product, so its algorithmic peak is a third of
-# the BF16 one.
-PEAKS = {
+# Published MI355X peaks: dense MFMA (TFLOP/s) and HBM3E bandwidth.  A BF16x3
+# product issues three BF16 MFMA products per FP32-class product, so its
+# algorithmic peak is a third of the BF16 one.
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAKS = {
     "gemm_fp64": (78.6, "fp64 MFMA"),
     "gemm_fp32": (157.3, "fp32 MFMA"),
     "gemm_bf16x3": (2500.0 / 3.0, "bf16 MFMA 2500 / 3 products"),
-    "jacobi_round": (78.6, "fp64 MFMA"),
+    "jacobi_gram": (78.6, "fp64 MFMA"),
+    "jacobi_solve": (78.6, "fp64 MFMA"),
+    "jacobi_rotate": (78.6, "fp64 MFMA"),
 }
+
+
+def roofline_of(name: str, ms: float, launches: float, flops: float, nbytes: float) -> dict:
+    """Roofline entry of one kernel class: the bound is the one its arithmetic
+    intensity (algorithmic flops per algorithmic byte) puts it under."""
+    peak_tf, basis = MFMA_PEAKS[name]
+    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
+    t = ms * 1e-3
+    if nbytes > 0 and (flops / nbytes) < ridge:
+        achieved = nbytes / t / 1e9 if t > 0 else 0.0
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "peak_basis": "HBM3E"}
+    achieved = flops / t / 1e12 if t > 0 else 0.0
+    return {"bound": "mfma", "achieved": achieved, "peak": peak_tf, "unit": "TFLOP/s",
+            "frac": achieved / peak_tf, "peak_basis": basis}
 
 
 def say(msg: str) -> None:
@@ -141,17 +159,15 @@ def main():
     say(f"forward sweeps: {sweeps_per_s:.3f} sweeps/s")
 
     dom = max(timing, key=lambda k: timing[k][0])
-    ms, launches, work = timing[dom]
-    peak, basis = PEAKS[dom]
-    achieved = (work / launches) / (ms / launches * 1e-3) / 1e12 if launches else 0.0
+    ms, launches, flops, nbytes = timing[dom]
     total_ms = sum(v[0] for v in timing.values())
-    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "kernel": dom, "peak_basis": basis,
-            "launches": int(launches), "avg_launch_us": 1e3 * ms / launches if launches else None,
-            "share_of_timed_kernels": ms / total_ms if total_ms else None,
-            "classes": {k: {"ms": v[0], "launches": int(v[1]),
-                            "tflops": (v[2] / (v[0] * 1e-3) / 1e12) if v[0] else None}
-                        for k, v in timing.items()}}
+    roof = roofline_of(dom, ms, launches, flops, nbytes)
+    roof.update({"traffic": None, "kernel": dom, "launches": int(launches),
+                 "avg_launch_us": 1e3 * ms / launches if launches else None,
+                 "share_of_timed_kernels": ms / total_ms if total_ms else None,
+                 "classes": {k: dict(ms=v[0], launches=int(v[1]), **{kk: vv for kk, vv in
+                                     roofline_of(k, *v).items() if kk in ("bound", "achieved", "unit", "frac")})
+                             for k, v in timing.items() if v[1] > 0}})
 
     cpu = None
     if not args.no_cpu_baseline:

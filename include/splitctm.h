@@ -126,26 +126,35 @@ ctm_status ctm_last_stats(ctm_ctx* ctx, double* gemm_flops, double* svd_sweeps);
 /* Diagnostics: the kernels behind the calls above, exposed for kernel-level
  * checks.  ctm_debug_gemm: C[M][N] = op(A) op(B), row-major, prec CTM_FP64
  * (double) or CTM_FP32 / CTM_BF16X3 (float); transA: A stored K x M, transB: B
- * stored N x K.  ctm_debug_svd: batch n x n FP64 matrices M (row-major,
- * consecutive) -> U S V^T, S descending; work = ctm_debug_svd_work_bytes
- * bytes of device memory; *sweeps in: sweep cap (<= 0: 60), out: sweeps run.
- * Both synchronise the stream. */
+ * stored N x K.  work: NULL, or device scratch of ctm_debug_gemm_work_bytes
+ * bytes; when that size is nonzero (long K, few 64 x 64 output tiles) the
+ * product runs split over K, as the contractions of the library do.
+ * ctm_debug_svd: batch n x n FP64 matrices M (row-major, consecutive) ->
+ * U S V^T, S descending; work = ctm_debug_svd_work_bytes bytes of device
+ * memory; *sweeps in: sweep cap (<= 0: 60), out: sweeps run.  Both
+ * synchronise the stream. */
+size_t ctm_debug_gemm_work_bytes(int prec, int M, int N, int K);
 ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K, const void* A, const void* B,
-                          void* C, void* hip_stream);
+                          void* C, void* work, void* hip_stream);
 size_t ctm_debug_svd_work_bytes(int n, int batch);
 ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S, double* V, void* work,
                          int* sweeps, void* hip_stream);
 
-/* Kernel timing (diagnostics): when enabled, every launch of the timed kernel
- * classes made by this context is bracketed by HIP events on the context's
- * stream; after each call the elapsed times are added up per class.
- * Enabling (or disabling) resets the totals.  Classes: 0 GEMM FP64, 1 GEMM
- * FP32, 2 GEMM BF16x3, 3 Jacobi round of the projector SVD.  *ms = summed
- * kernel time, *launches = number of launches, *work = algorithmic flops of
- * those launches (GEMM: 2 M N K per product; Jacobi round: the Gram matrix and
- * the rotation of G and V for every block pair of the round). */
+/* Kernel timing (diagnostics): when enabled, every launch of a timed kernel
+ * class made by this context carries a start and a stop event recorded by the
+ * runtime at the start and the end of that kernel on the context's stream;
+ * after each call the elapsed times are added up per class.  Enabling (or
+ * disabling) resets the totals.  Classes: 0 GEMM FP64, 1 GEMM FP32, 2 GEMM
+ * BF16x3, 3 Jacobi Gram matrices, 4 Jacobi 32 x 32 eigensolves, 5 Jacobi
+ * rotations of G and V.  *ms = summed kernel time, *launches = number of
+ * launches, *flops and *bytes = algorithmic work and memory traffic of those
+ * launches (GEMM: 2 M N K flops and the operands read and written once;
+ * Gram: the pairs' columns read once; eigensolve: partial Gram matrices read
+ * and rotations written; rotation: the rotated columns of G and V read and
+ * written once, counted on the device for the pairs that were rotated). */
 ctm_status ctm_kernel_timing_enable(ctm_ctx* ctx, int on);
-ctm_status ctm_kernel_timing(ctm_ctx* ctx, int kernel_class, double* ms, double* launches, double* work);
+ctm_status ctm_kernel_timing(ctm_ctx* ctx, int kernel_class, double* ms, double* launches, double* flops,
+                             double* bytes);
 
 void ctm_destroy(ctm_ctx* ctx);
 const char* ctm_strerror(ctm_status s);

@@ -20,6 +20,9 @@ conventional_ctmrg
     projectors, sharing no code with split_ctmrg.
 
 Parity status: the teal and red half networks are a reading of the paper
-(their figures are missing from the source); they are pinned only indirectly
-(Ising closed forms, product states, agreement with the conventional CTMRG).
+(their figures are missing from the source); they are pinned end to end only
+(Ising closed forms, product states, agreement with the conventional CTMRG,
+2x2 cell = 1x1 cell for a translation-invariant state), not network by
+network: "parity unpinned" at the level of the individual teal / red
+networks.
 """

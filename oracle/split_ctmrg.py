@@ -11,12 +11,17 @@ Leg conventions are those of paper_2502_10298_amd.inputs (ring order, first /
 second split transfer tensor along each edge).
 
 Readings of the paper (it is silent or its figures are missing):
-  * teal / red half networks (their figure bodies are missing): the
-    intermediate environment after the ket half-step, i.e. the 1-column patch
-    with the green and yellow projectors already inserted (App. A says the
-    teal/red networks contain the green/yellow projectors).  Parity unpinned
-    against the paper itself; pinned indirectly (Ising, product states,
-    convergence to the conventional CTMRG).
+  * teal / red half networks (their figure bodies are missing): a 2-column
+    patch made of the left environment after the ket half-step (green and
+    yellow projectors inserted, as App. A requires), the bra layer of column
+    y, the ket layer of column y+1 and the right environment after a
+    bra-first half-step (green' / yellow' projectors: the same networks cut on
+    the other legs).  A 1-column patch leaves chi_E stuck at 1 from the
+    identity boundary, since every teal cut then carries a single environment
+    bond.  No figure of the paper fixes these networks, so they are pinned
+    end to end only: Ising free energy and magnetisation against Onsager,
+    product states, agreement with the conventional double-layer CTMRG as
+    chi grows, a translation-invariant 2x2 cell equal to the 1x1 cell.
   * singular values below cutoff * s_1 are dropped (cutoff 1e-12);
   * canonical sign: the entry of largest magnitude of every column of P_T is
     made positive (lowest index on ties), flipping the matching column of P_B;

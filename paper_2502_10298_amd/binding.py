@@ -22,9 +22,10 @@ INIT = {"identity": 0, "product": 1}
 
 EXPORTED = ("ctm_workspace_size", "ctm_init", "ctm_sweep", "ctm_projectors", "ctm_projectors_elems",
             "ctm_energy", "ctm_energy_grad", "ctm_env_elems", "ctm_env_export", "ctm_env_import",
-            "ctm_last_stats", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd",
+            "ctm_last_stats", "ctm_debug_gemm_work_bytes", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd",
             "ctm_kernel_timing_enable", "ctm_kernel_timing", "ctm_destroy", "ctm_strerror")
-KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "gemm_bf16x3": 2, "jacobi_round": 3}
+KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "gemm_bf16x3": 2, "jacobi_gram": 3, "jacobi_solve": 4,
+                  "jacobi_rotate": 5}
 
 
 class CtmError(RuntimeError):
@@ -64,11 +65,12 @@ def lib() -> ctypes.CDLL:
         "ctm_env_export": (I, [P, P]),
         "ctm_env_import": (I, [P, P]),
         "ctm_last_stats": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
-        "ctm_debug_gemm": (I, [I, I, I, I, I, I, P, P, P, P]),
+        "ctm_debug_gemm_work_bytes": (S, [I, I, I, I]),
+        "ctm_debug_gemm": (I, [I, I, I, I, I, I, P, P, P, P, P]),
         "ctm_debug_svd_work_bytes": (S, [I, I]),
         "ctm_debug_svd": (I, [I, I, P, P, P, P, P, ctypes.POINTER(I), P]),
         "ctm_kernel_timing_enable": (I, [P, I]),
-        "ctm_kernel_timing": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "ctm_kernel_timing": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
         "ctm_destroy": (None, [P]),
         "ctm_strerror": (ctypes.c_char_p, [I]),
     }
@@ -217,14 +219,14 @@ class SplitCTM:
             raise CtmError(st, "ctm_kernel_timing_enable")
 
     def kernel_timing(self):
-        """{class: (ms, launches, work)} summed since kernel_timing_enable."""
+        """{class: (ms, launches, flops, bytes)} summed since kernel_timing_enable."""
         out = {}
         for name, k in KERNEL_CLASSES.items():
-            ms, n, w = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
-            st = lib().ctm_kernel_timing(self.h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(w))
+            v = [ctypes.c_double(0) for _ in range(4)]
+            st = lib().ctm_kernel_timing(self.h, k, *[ctypes.byref(x) for x in v])
             if st != CTM_OK:
                 raise CtmError(st, "ctm_kernel_timing")
-            out[name] = (ms.value, n.value, w.value)
+            out[name] = tuple(x.value for x in v)
         return out
 
     def stats(self):
@@ -234,14 +236,17 @@ class SplitCTM:
         return f.value, s.value
 
 
-def debug_gemm(A, B, transA=False, transB=False, prec="fp64", stream=None):
+def debug_gemm(A, B, transA=False, transB=False, prec="fp64", stream=None, split_k=True):
     import torch
     M = A.shape[1] if transA else A.shape[0]
     K = A.shape[0] if transA else A.shape[1]
     N = B.shape[0] if transB else B.shape[1]
     C = torch.empty((M, N), dtype=A.dtype, device=A.device)
+    wb = lib().ctm_debug_gemm_work_bytes(PREC[prec], M, N, K) if split_k else 0
+    work = torch.empty(max(wb, 1), dtype=torch.uint8, device=A.device) if wb else None
     st = lib().ctm_debug_gemm(PREC[prec], int(transA), int(transB), M, N, K, _ptr(A.contiguous()),
-                              _ptr(B.contiguous()), _ptr(C), _stream_ptr(torch, stream))
+                              _ptr(B.contiguous()), _ptr(C), _ptr(work) if work is not None else None,
+                              _stream_ptr(torch, stream))
     if st != CTM_OK:
         raise CtmError(st, "ctm_debug_gemm")
     return C

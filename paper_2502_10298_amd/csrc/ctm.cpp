@@ -541,6 +541,7 @@ void begin(ctm_ctx* c) {
   c->E.ar.overflow = false;
   c->E.ar.release(c->transient_mark);
   c->E.clear_tape();
+  c->E.svdc_reset();
   kernel_timer() = c->timing ? &c->timer : nullptr;
 }
 
@@ -712,6 +713,17 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, int n_sweeps, int 
   for (auto& t : mv) t = E.alloc(E.cdt, {env_n});
   Ten genv = E.alloc(E.cdt, {env_n});
   Ten gA = E.alloc(F64, {c->A64.n()});
+  // SVD record / replay store: one slot per move of a checkpoint block, each
+  // bounded by the decompositions of every site of the cell (green, green',
+  // teal: n = chi_E D; yellow, yellow', red: n = chi_I p D)
+  {
+    const long nE = (long)c->chiE * c->D, nI = (long)c->chiI * c->p * c->D;
+    const long per_site = 3 * (2 * nE * nE + nE) + 3 * (2 * nI * nI + nI);
+    const long per_slot = (long)c->Lx * c->Ly * per_site + 32L * 8 * (c->Lx + c->Ly) * 4;
+    Ten buf = E.alloc(F64, {4L * ckpt, per_slot});
+    E.svdc_setup(buf, 4 * ckpt, per_slot);
+  }
+  const int s_last = (nblk - 1) * ckpt;   // first sweep of the last block
   Ten ebuf = E.alloc(F64, {(long)c->Lx * c->Ly * 4});
   E.zero(gA);
   if (!E.dry && E.ok()) {
@@ -729,11 +741,13 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, int n_sweeps, int 
       E.check(hipMemcpyAsync(c->cur_blk.p, src.p, src.bytes(), hipMemcpyDeviceToDevice, E.s));
     for (int dir = 0; dir < 4 && E.ok(); ++dir) {
       size_t mk = E.ar.mark();
+      E.svdc_select(s >= s_last ? (s - s_last) * 4 + dir : -1, 1);
       Env env = view_env(*c, c->cur_blk);
       Env out = do_move(*c, env, A, dir);
       store_env(*c, out, c->cur_blk);
       E.ar.release(mk);
     }
+    E.svdc_select(-1, 0);
     if ((s + 1) % ckpt == 0 && (s + 1) / ckpt <= nblk && !E.dry && E.ok())
       E.check(hipMemcpyAsync(ck[(s + 1) / ckpt].p, c->cur_blk.p, c->cur_blk.bytes(), hipMemcpyDeviceToDevice, E.s));
     if (E.dry) break;   // the workspace peak repeats every sweep
@@ -796,6 +810,8 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, int n_sweeps, int 
     // regenerate the environments at every move of the block (untaped)
     if (!E.dry && E.ok())
       E.check(hipMemcpyAsync(c->cur_blk.p, ck[b].p, ck[b].bytes(), hipMemcpyDeviceToDevice, E.s));
+    if (b != nblk - 1)   // the slots hold a later block: re-record (the block's last move recomputes)
+      for (auto& sl : E.svdc_slots) sl.valid = false;
     int nm = 0;
     for (int s = s0; s < s1 && E.ok(); ++s)
       for (int dir = 0; dir < 4 && E.ok(); ++dir) {
@@ -804,12 +820,14 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, int n_sweeps, int 
         ++nm;
         if (s == s1 - 1 && dir == 3) break;   // the last move's input is enough
         size_t mk = E.ar.mark();
+        E.svdc_select((s - s0) * 4 + dir, b == nblk - 1 ? 2 : 1);
         Env env = view_env(*c, c->cur_blk);
         Env out = do_move(*c, env, A, dir);
         store_env(*c, out, c->cur_blk);
         E.ar.release(mk);
         if (E.dry) break;
       }
+    E.svdc_select(-1, 0);
     // reverse the moves of the block
     for (int m = nm - 1; m >= 0 && E.ok(); --m) {
       const int dir = m % 4;
@@ -822,7 +840,9 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, int n_sweeps, int 
         t.id = E.next_id++;
         E.mark_input(t);
       }
+      E.svdc_select(m, 2);
       Env out = do_move(*c, env, Ai, dir);
+      E.svdc_select(-1, 0);
       E.taping = false;
       // seed with the cotangent of the move's output
       Env gv = view_env(*c, genv);
@@ -1119,17 +1139,29 @@ ctm_status ctm_env_import(ctm_ctx* c, const double* env_dev) {
   return (ctm_status)status_from_engine(E);
 }
 
+size_t ctm_debug_gemm_work_bytes(int prec, int M, int N, int K) {
+  return (size_t)splitk_scratch_elems(M, N, K) * (prec == CTM_FP64 ? 8 : 4);
+}
+
 ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K, const void* A, const void* B,
-                          void* C, void* stream) {
+                          void* C, void* work, void* stream) {
   if (M < 0 || N < 0 || K < 1 || !A || !B || !C || prec < 0 || prec > 2) return CTM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const long lda = transA ? M : K, ldb = transB ? K : N;
+  const bool split = work && splitk_scratch_elems(M, N, K) > 0;
   hipError_t e;
   if (prec == CTM_FP64)
-    e = gemm_f64(s, transA, transB, M, N, K, 1.0, (const double*)A, lda, 0, (const double*)B, ldb, 0, 0.0, (double*)C, N, 0, 1);
-  else
-    e = gemm_f32(s, prec == CTM_FP32 ? Prec::F32 : Prec::BF16X3, transA, transB, M, N, K, 1.f, (const float*)A, lda, 0,
-                 (const float*)B, ldb, 0, 0.f, (float*)C, N, 0, 1);
+    e = split ? gemm_f64_splitk(s, transA, transB, M, N, K, 1.0, (const double*)A, lda, (const double*)B, ldb, 0.0,
+                                (double*)C, N, (double*)work)
+              : gemm_f64(s, transA, transB, M, N, K, 1.0, (const double*)A, lda, 0, (const double*)B, ldb, 0, 0.0,
+                         (double*)C, N, 0, 1);
+  else {
+    const Prec md = prec == CTM_FP32 ? Prec::F32 : Prec::BF16X3;
+    e = split ? gemm_f32_splitk(s, md, transA, transB, M, N, K, 1.f, (const float*)A, lda, (const float*)B, ldb, 0.f,
+                                (float*)C, N, (float*)work)
+              : gemm_f32(s, md, transA, transB, M, N, K, 1.f, (const float*)A, lda, 0, (const float*)B, ldb, 0, 0.f,
+                         (float*)C, N, 0, 1);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e == hipSuccess ? CTM_OK : CTM_EDEVICE;
 }
@@ -1154,11 +1186,13 @@ ctm_status ctm_kernel_timing_enable(ctm_ctx* c, int on) {
   return CTM_OK;
 }
 
-ctm_status ctm_kernel_timing(ctm_ctx* c, int kernel_class, double* ms, double* launches, double* work) {
+ctm_status ctm_kernel_timing(ctm_ctx* c, int kernel_class, double* ms, double* launches, double* flops,
+                             double* bytes) {
   if (!c || kernel_class < 0 || kernel_class >= KC_COUNT) return CTM_EINVAL;
   if (ms) *ms = c->timer.ms[kernel_class];
   if (launches) *launches = c->timer.launches[kernel_class];
-  if (work) *work = c->timer.work[kernel_class];
+  if (flops) *flops = c->timer.flops[kernel_class];
+  if (bytes) *bytes = c->timer.bytes[kernel_class];
   return CTM_OK;
 }
 

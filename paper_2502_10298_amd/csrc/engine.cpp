@@ -218,6 +218,22 @@ Ten Engine::normalize(const Ten& A) {
 void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten& A, long offA, long lda,
                   const Ten& B, long offB, long ldb, double beta, const Ten& C, long offC, long ldc) {
   flops_gemm += 2L * M * N * K;
+  // Split-K (long K, few output tiles): the scratch for the slices comes from the arena
+  const long sk = splitk_scratch_elems(M, N, K);
+  if (sk > 0) {
+    size_t mk = ar.mark();
+    Ten P = alloc(C.dt, {sk});
+    if (!dry && ok()) {
+      if (C.dt == F64)
+        check(gemm_f64_splitk(s, tA, tB, M, N, K, alpha, A.f64() + offA, lda, B.f64() + offB, ldb, beta,
+                              C.f64() + offC, ldc, P.f64()));
+      else
+        check(gemm_f32_splitk(s, prec == Prec::BF16X3 ? Prec::BF16X3 : Prec::F32, tA, tB, M, N, K, (float)alpha,
+                              A.f32() + offA, lda, B.f32() + offB, ldb, (float)beta, C.f32() + offC, ldc, P.f32()));
+    }
+    ar.release(mk);
+    return;
+  }
   if (dry || !ok()) return;
   if (M <= 0 || N <= 0) return;
   if (K <= 0) {   // C = beta C
@@ -232,12 +248,27 @@ void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten
     }
     return;
   }
+  static const bool timed = [] {
+    const char* e = getenv("SPLITCTM_TRACE");
+    return e && atoi(e) >= 2;
+  }();
+  std::chrono::steady_clock::time_point t0;
+  if (timed) {
+    check(hipStreamSynchronize(s));
+    t0 = std::chrono::steady_clock::now();
+  }
   if (C.dt == F64)
     check(gemm_f64(s, tA, tB, M, N, K, alpha, A.f64() + offA, lda, 0, B.f64() + offB, ldb, 0, beta,
                    C.f64() + offC, ldc, 0, 1));
   else
     check(gemm_f32(s, prec == Prec::BF16X3 ? Prec::BF16X3 : Prec::F32, tA, tB, M, N, K, (float)alpha,
                    A.f32() + offA, lda, 0, B.f32() + offB, ldb, 0, (float)beta, C.f32() + offC, ldc, 0, 1));
+  if (timed) {
+    check(hipStreamSynchronize(s));
+    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    fprintf(stderr, "[gemm] dt=%d tA=%d tB=%d M=%d N=%d K=%d lda=%ld ldb=%ld ldc=%ld us=%.1f\n", C.dt, (int)tA, (int)tB,
+            M, N, K, lda, ldb, ldc, us);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -619,7 +650,25 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
                                  hipMemcpyDeviceToDevice, s));
       }
       void* work = ar.alloc(svd_work_bytes((int)nb, g));
-      if (!dry && ok()) {
+      // replay a recorded decomposition of the same matrices
+      bool replayed = false;
+      if (svdc_mode == 2 && svdc_slot >= 0) {
+        SvdCacheSlot& sl = svdc_slots[svdc_slot];
+        if (sl.valid && svdc_cursor < sl.off.size() && sl.nb[svdc_cursor] == nb && sl.g[svdc_cursor] == g) {
+          if (!dry && ok()) {
+            const double* src = svdc_buf.f64() + (long)svdc_slot * svdc_per_slot + sl.off[svdc_cursor];
+            const long un = (long)g * nb * nb, sn = (long)g * nb;
+            check(hipMemcpyAsync(Ub.p, src, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
+            check(hipMemcpyAsync(Sb.p, src + un, sizeof(double) * sn, hipMemcpyDeviceToDevice, s));
+            check(hipMemcpyAsync(Vb.p, src + un + sn, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
+          }
+          ++svdc_cursor;
+          replayed = true;
+        } else {
+          sl.valid = false;   // out of step with the recording: recompute from here on
+        }
+      }
+      if (!replayed && !dry && ok()) {
         int sweeps = 0;
         static const bool trace = getenv("SPLITCTM_SVD_TRACE") != nullptr;
         auto t0 = std::chrono::steady_clock::now();
@@ -638,6 +687,25 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
           const int kc = std::min<long>(reqs[grp[0]].chi, nb) - 1;
           fprintf(stderr, "[svd] n=%ld batch=%d warm=%d sweeps=%d %.1f ms rank=%d s_chi/s1=%.2e s_2chi/s1=%.2e\n", nb, g,
                   (int)warm_all, sweeps, ms, r, sv[kc] / sv[0], sv[std::min<long>(2 * kc + 1, nb - 1)] / sv[0]);
+        }
+      }
+      if (!replayed && svdc_mode == 1 && svdc_slot >= 0) {   // record
+        SvdCacheSlot& sl = svdc_slots[svdc_slot];
+        const long un = (long)g * nb * nb, sn = (long)g * nb;
+        const long need = ((2 * un + sn + 31) / 32) * 32;
+        if (sl.valid && sl.used + need <= sl.cap) {
+          if (!dry && ok()) {
+            double* dst = svdc_buf.f64() + (long)svdc_slot * svdc_per_slot + sl.used;
+            check(hipMemcpyAsync(dst, Ub.p, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
+            check(hipMemcpyAsync(dst + un, Sb.p, sizeof(double) * sn, hipMemcpyDeviceToDevice, s));
+            check(hipMemcpyAsync(dst + un + sn, Vb.p, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
+          }
+          sl.off.push_back(sl.used);
+          sl.nb.push_back(nb);
+          sl.g.push_back(g);
+          sl.used += need;
+        } else {
+          sl.valid = false;   // a later replay of this move recomputes everything
         }
       }
       ar.release(mk);

@@ -152,6 +152,46 @@ struct Engine {
   std::vector<Ten> warm;
   std::vector<char> warm_valid;
   long svd_calls = 0;
+  // Record / replay of projector SVDs per move of a checkpoint block: the
+  // recomputation of a move rebuilds bit-identical matrices M, so the U, S, V
+  // recorded when the move first ran are reused instead of recomputed.
+  struct SvdCacheSlot {
+    long cap = 0, used = 0;
+    bool valid = false;
+    std::vector<long> off, nb, g;
+  };
+  Ten svdc_buf;                      // FP64, nslots * per_slot elements
+  long svdc_per_slot = 0;
+  std::vector<SvdCacheSlot> svdc_slots;
+  int svdc_mode = 0;                 // 0 off, 1 record, 2 replay
+  int svdc_slot = -1;
+  size_t svdc_cursor = 0;
+  void svdc_setup(const Ten& buf, int nslots, long per_slot_elems) {
+    svdc_buf = buf;
+    svdc_per_slot = per_slot_elems;
+    svdc_slots.assign(nslots, SvdCacheSlot{});
+    for (auto& sl : svdc_slots) sl.cap = per_slot_elems;
+    svdc_mode = 0;
+    svdc_slot = -1;
+  }
+  void svdc_select(int slot, int mode) {
+    svdc_slot = (slot >= 0 && slot < (int)svdc_slots.size()) ? slot : -1;
+    svdc_mode = svdc_slot >= 0 ? mode : 0;
+    svdc_cursor = 0;
+    if (svdc_mode == 1) {
+      SvdCacheSlot& sl = svdc_slots[svdc_slot];
+      sl.used = 0;
+      sl.valid = true;
+      sl.off.clear();
+      sl.nb.clear();
+      sl.g.clear();
+    }
+  }
+  void svdc_reset() {
+    svdc_slots.clear();
+    svdc_mode = 0;
+    svdc_slot = -1;
+  }
   Ten bond_energy(const Ten& rho, const Ten& h64, int p);   // -> FP64 [2] (e, den)
 
   // ---- low level ----

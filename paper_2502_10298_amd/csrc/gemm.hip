@@ -22,6 +22,8 @@
 // use the same k slot order, so only the output layout matters.
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace sctm {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -250,17 +252,17 @@ hipError_t gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double
                     double beta, double* C, long ldc, long sC, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   dim3 g = gemm_grid(M, N, batch);
-  KernelTimer* tm = kernel_timer();
-  if (tm) tm->begin(s, KC_GEMM_F64, 2.0 * M * N * (double)K * batch);
+  const int kind = KC_GEMM_F64;
+  const double fl = 2.0 * M * N * (double)K * batch;
+  const double by = 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1));
   if (!tA && !tB)
-    hipLaunchKernelGGL((gemm_kernel<double, d4, false, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else if (tA && !tB)
-    hipLaunchKernelGGL((gemm_kernel<double, d4, true, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else if (!tA && tB)
-    hipLaunchKernelGGL((gemm_kernel<double, d4, false, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else
-    hipLaunchKernelGGL((gemm_kernel<double, d4, true, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-  if (tm) tm->end(s);
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   return hipGetLastError();
 }
 
@@ -269,29 +271,88 @@ hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, in
                     float* C, long ldc, long sC, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   dim3 g = gemm_grid(M, N, batch);
-  KernelTimer* tm = kernel_timer();
-  if (tm) tm->begin(s, mode == Prec::BF16X3 ? KC_GEMM_BF16X3 : KC_GEMM_F32, 2.0 * M * N * (double)K * batch);
+  const int kind = mode == Prec::BF16X3 ? KC_GEMM_BF16X3 : KC_GEMM_F32;
+  const double fl = 2.0 * M * N * (double)K * batch;
+  const double by = 4.0 * batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.f ? 2 : 1));
   if (mode == Prec::BF16X3) {
     if (!tA && !tB)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+      launch_timed(kind, fl, by, gemm_bf16x3_kernel<false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
     else if (tA && !tB)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+      launch_timed(kind, fl, by, gemm_bf16x3_kernel<true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
     else if (!tA && tB)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+      launch_timed(kind, fl, by, gemm_bf16x3_kernel<false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
     else
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-    if (tm) tm->end(s);
-  return hipGetLastError();
+      launch_timed(kind, fl, by, gemm_bf16x3_kernel<true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    return hipGetLastError();
   }
   if (!tA && !tB)
-    hipLaunchKernelGGL((gemm_kernel<float, f4, false, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<float, f4, false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else if (tA && !tB)
-    hipLaunchKernelGGL((gemm_kernel<float, f4, true, false>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<float, f4, true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else if (!tA && tB)
-    hipLaunchKernelGGL((gemm_kernel<float, f4, false, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<float, f4, false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else
-    hipLaunchKernelGGL((gemm_kernel<float, f4, true, true>), g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<float, f4, true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Split-K: a product whose 64 x 64 output tiles are too few to fill the chip
+// and whose K is long runs as a strided batch of K slices into a scratch
+// buffer; one more pass adds the slices in order and applies alpha and beta.
+static int splitk_slices(int M, int N, int K) {
+  const long tiles = (long)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  if (M <= 0 || N <= 0 || tiles >= 128 || K < 1024) return 0;
+  int S = (int)std::min<long>(std::min<long>(512 / tiles, K / 256), 64);
+  while (S > 1 && (long)S * M * N > (16L << 20)) S /= 2;
+  return S >= 2 ? S : 0;
+}
+
+long splitk_scratch_elems(int M, int N, int K) {
+  const int S = splitk_slices(M, N, K);
+  return S ? (long)S * M * N : 0;
+}
+
+template <typename T, typename Launch, typename Reduce>
+static hipError_t splitk_run(bool tA, bool tB, int M, int N, int K, long lda, long ldb, Launch launch,
+                             Reduce reduce) {
+  const int S = splitk_slices(M, N, K);
+  const int Ks = (K + S - 1) / S;
+  const int full = K / Ks;            // slices of length Ks
+  const int rest = K - full * Ks;     // one shorter slice (may be 0)
+  const long aStep = tA ? (long)Ks * lda : Ks, bStep = tB ? (long)Ks : (long)Ks * ldb;
+  const long mn = (long)M * N;
+  hipError_t e = launch(Ks, 0L, 0L, 0L, aStep, bStep, mn, full);
+  if (e == hipSuccess && rest > 0) e = launch(rest, full * aStep, full * bStep, full * mn, 0L, 0L, 0L, 1);
+  if (e == hipSuccess) e = reduce(full + (rest > 0 ? 1 : 0));
+  return e;
+}
+
+hipError_t gemm_f64_splitk(hipStream_t s, bool tA, bool tB, int M, int N, int K, double alpha, const double* A,
+                           long lda, const double* B, long ldb, double beta, double* C, long ldc, double* scratch) {
+  if (!splitk_slices(M, N, K))
+    return gemm_f64(s, tA, tB, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+  return splitk_run<double>(
+      tA, tB, M, N, K, lda, ldb,
+      [&](int k, long oA, long oB, long oP, long sA, long sB, long sP, int nb) {
+        return gemm_f64(s, tA, tB, M, N, k, 1.0, A + oA, lda, sA, B + oB, ldb, sB, 0.0, scratch + oP, N, sP, nb);
+      },
+      [&](int nsl) { return splitk_reduce_f64(s, scratch, nsl, M, N, alpha, beta, C, ldc); });
+}
+
+hipError_t gemm_f32_splitk(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, int K, float alpha,
+                           const float* A, long lda, const float* B, long ldb, float beta, float* C, long ldc,
+                           float* scratch) {
+  if (!splitk_slices(M, N, K))
+    return gemm_f32(s, mode, tA, tB, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+  return splitk_run<float>(
+      tA, tB, M, N, K, lda, ldb,
+      [&](int k, long oA, long oB, long oP, long sA, long sB, long sP, int nb) {
+        return gemm_f32(s, mode, tA, tB, M, N, k, 1.f, A + oA, lda, sA, B + oB, ldb, sB, 0.f, scratch + oP, N, sP,
+                        nb);
+      },
+      [&](int nsl) { return splitk_reduce_f32(s, scratch, nsl, M, N, alpha, beta, C, ldc); });
 }
 
 }  // namespace sctm

@@ -37,6 +37,18 @@ hipError_t fill_f32(hipStream_t s, float* p, float v, long n);
 hipError_t cast_f32_to_f64(hipStream_t s, const float* in, double* out, long n);
 hipError_t cast_f64_to_f32(hipStream_t s, const double* in, float* out, long n);
 hipError_t axpy_f64(hipStream_t s, double a, const double* x, double* y, long n);
+// Split-K products (used when the output has few tiles and K is long; else a
+// plain product): scratch = splitk_scratch_elems(M, N, K) elements.
+long splitk_scratch_elems(int M, int N, int K);
+hipError_t gemm_f64_splitk(hipStream_t s, bool tA, bool tB, int M, int N, int K, double alpha, const double* A,
+                           long lda, const double* B, long ldb, double beta, double* C, long ldc, double* scratch);
+hipError_t gemm_f32_splitk(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, int K, float alpha,
+                           const float* A, long lda, const float* B, long ldb, float beta, float* C, long ldc,
+                           float* scratch);
+hipError_t splitk_reduce_f64(hipStream_t s, const double* P, int S, int M, int N, double alpha, double beta, double* C,
+                             long ldc);
+hipError_t splitk_reduce_f32(hipStream_t s, const float* P, int S, int M, int N, float alpha, float beta, float* C,
+                             long ldc);
 hipError_t axpy_f32(hipStream_t s, float a, const float* x, float* y, long n);
 // Two-pass deterministic sum of squares -> *out (device, FP64).
 hipError_t sumsq_f64(hipStream_t s, const double* x, long n, double* partial, double* out);

@@ -141,6 +141,33 @@ hipError_t axpy_f32(hipStream_t s, float a, const float* x, float* y, long n) {
   return hipGetLastError();
 }
 
+// split-K epilogue: C[m][n] = alpha sum_s P[s][m][n] + beta C[m][n], the
+// slices added in order (P: S consecutive M x N blocks, C: leading dim ldc)
+template <typename T>
+__global__ void splitk_reduce_kernel(const T* P, int S, int M, int N, T alpha, T beta, T* C, long ldc) {
+  const long mn = (long)M * N;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < mn; e += (long)gridDim.x * blockDim.x) {
+    T a = 0;
+    for (int k = 0; k < S; ++k) a += P[(long)k * mn + e];
+    const long o = (e / N) * ldc + e % N;
+    C[o] = (beta == T(0)) ? alpha * a : alpha * a + beta * C[o];
+  }
+}
+hipError_t splitk_reduce_f64(hipStream_t s, const double* P, int S, int M, int N, double alpha, double beta, double* C,
+                             long ldc) {
+  const long n = (long)M * N;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, P, S, M, N, alpha, beta, C, ldc);
+  return hipGetLastError();
+}
+hipError_t splitk_reduce_f32(hipStream_t s, const float* P, int S, int M, int N, float alpha, float beta, float* C,
+                             long ldc) {
+  const long n = (long)M * N;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, P, S, M, N, alpha, beta, C, ldc);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // reductions: pass 1 writes RED_BLOCKS partials, pass 2 sums them in order.
 // ---------------------------------------------------------------------------

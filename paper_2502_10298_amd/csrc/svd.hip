@@ -4,10 +4,10 @@
 // The columns of G = M are orthogonalised by orthogonal rotations G <- G W,
 // accumulated in V <- V W; at convergence G = U S.  Columns are grouped in
 // blocks of 16; a round-robin tournament pairs the blocks so that every
-// round updates disjoint column sets in parallel (one workgroup per block
-// pair).  A workgroup forms the 32 x 32 Gram matrix of its two blocks from
-// the actual columns, diagonalises it with a cyclic two-sided Jacobi in LDS,
-// and applies the resulting rotation to the 32 columns of G and of V.
+// round updates disjoint column sets in parallel.  For each block pair the
+// 32 x 32 Gram matrix of its columns is formed from the actual columns,
+// diagonalised with a cyclic two-sided Jacobi in LDS, and the resulting
+// rotation is applied to the 32 columns of G and of V.
 // Convergence: every pair's largest relative off-diagonal
 // |g_i . g_j| / (|g_i| |g_j|) below tol in a whole sweep.  W is a product
 // of plane rotations, so the method is backward stable (the result is the
@@ -30,9 +30,9 @@ static constexpr int JP = 2 * JW;    // columns per block pair
 static inline int padded(int n) { return ((n + JP - 1) / JP) * JP; }
 
 struct SvdLayout {
-  int np, nb, pairs, rounds;
+  int np, nb, pairs, rounds, nchG, nchV;
   long sG, sV, sOff;
-  size_t offG, offV, offOff, offNorm, offRank, offDone, offFro, total;
+  size_t offG, offV, offOff, offNorm, offRank, offDone, offFro, offPart, offW, offRot, offCnt, total;
 };
 
 static SvdLayout layout(int n, int batch) {
@@ -44,6 +44,8 @@ static SvdLayout layout(int n, int batch) {
   L.sG = (long)L.np * n;
   L.sV = (long)L.np * L.np;
   L.sOff = (long)L.pairs * L.rounds;
+  L.nchG = (n + 255) / 256;
+  L.nchV = (L.np + 255) / 256;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -57,6 +59,10 @@ static SvdLayout layout(int n, int batch) {
   L.offRank = take(sizeof(int) * (size_t)L.np * batch);
   L.offDone = take(sizeof(int) * (size_t)batch);
   L.offFro = take(sizeof(double) * (size_t)batch);
+  L.offPart = take(sizeof(double) * (size_t)L.pairs * L.nchG * 1024 * batch);
+  L.offW = take(sizeof(double) * (size_t)L.pairs * 1024 * batch);
+  L.offRot = take(sizeof(int) * (size_t)L.pairs * batch);
+  L.offCnt = take(sizeof(unsigned long long));
   L.total = off;
   return L;
 }
@@ -66,7 +72,7 @@ size_t svd_work_bytes(int n, int batch) { return layout(n, batch).total; }
 // Gt = M^T (cold start) or only its padding rows (warm start: rows < n come
 // from Gt = (M V0)^T by GEMM); Vt = I or V0^T, padded with the identity.
 __global__ void svd_init_kernel(const double* M, const double* V0, int n, int np, double* Gt, double* Vt, int* done,
-                                long sG, long sV) {
+                                long sG, long sV, unsigned long long* cnt) {
   const int b = blockIdx.y;
   M += (long)b * n * n;
   if (V0) V0 += (long)b * n * n;
@@ -86,7 +92,10 @@ __global__ void svd_init_kernel(const double* M, const double* V0, int n, int np
       Vt[f] = (V0 && i < n && j < n) ? V0[i * n + j] : ((i == j) ? 1.0 : 0.0);
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) done[b] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    done[b] = 0;
+    if (b == 0) *cnt = 0;
+  }
 }
 
 __device__ inline void circle_pair(int players, int round, int idx, int& a, int& b) {
@@ -99,57 +108,61 @@ __device__ inline void circle_pair(int players, int round, int idx, int& a, int&
   }
 }
 
-// Four 64-wide wavefronts per block pair.  The rows of the 32 columns are
-// split over the waves: each wave forms a partial Gram matrix on the FP64
-// matrix cores (v_mfma_f64_16x16x4: A lane l holds A[l%16][l/16], B lane l
-// holds B[l/16][l%16], D lane l register r holds D[4r + l/16][l%16]), the
-// partials are summed in LDS, the 32 x 32 eigenproblem is solved in LDS, and
-// each wave rotates its share of the rows of G and V on the matrix cores.
+// One round of the tournament is three launches, each filling the chip:
+//   gram:   grid (pair, 256-entry chunk of the column length): the partial
+//           32 x 32 Gram matrix of the pair's columns over the chunk, on the
+//           FP64 matrix cores (v_mfma_f64_16x16x4: A lane l holds
+//           A[l%16][l/16], B lane l holds B[l/16][l%16], D lane l register r
+//           holds D[4r + l/16][l%16]);
+//   solve:  grid (pair): sums the partials in a fixed order (the result does
+//           not depend on scheduling), tests the pair and, unless it is
+//           converged, diagonalises the Gram matrix by cyclic two-sided
+//           Jacobi in LDS, giving the 32 x 32 rotation W;
+//   rotate: grid (pair, chunk of G or of V): new columns = old columns W,
+//           again on the matrix cores.
 //
-// A pair counts as orthogonal when |g_i . g_j| <= tol |g_i| |g_j| (relative
-// criterion: every singular triplet, small ones included, is fixed to
-// relative accuracy O(tol) when M is well conditioned up to column scaling).
-// Columns below 1e-15 |M|_F are rounding noise of the rotations themselves:
-// a pair of two such columns is never rotated and does not count.
+// A pair counts as orthogonal when
+//   |g_i . g_j| <= tol max(|g_i|, f) max(|g_j|, f),   f = 1e-13 |M|_F:
+// relative for columns above the floor f (every singular triplet above it is
+// fixed to relative accuracy O(tol)), absolute at the floor for columns below
+// it.  Columns that small carry the rounding noise of the rotations of the
+// large ones; asking them to be orthogonal in relative terms never converges
+// for a numerically rank-deficient M.
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void jacobi_round_kernel(double* Gt_all, double* Vt_all, int m, int np, int round,
-                                                           double tol, double* off_all, const int* done, long sG,
-                                                           long sV, long sOff, int inner_sweeps,
-                                                           const double* fro2_all) {
-  const int b = blockIdx.y;
+static constexpr int JCH = 256;      // column-length entries per chunk (4 waves x 64)
+
+__global__ __launch_bounds__(256) void jacobi_gram_kernel(const double* Gt_all, int m, int np, int round, long sG,
+                                                          double* part_all, int nchunk, const int* done) {
+  const int b = blockIdx.z;
   if (done[b]) return;
-  double* Gt = Gt_all + b * sG;
-  double* Vt = Vt_all + b * sV;
-  double* offv = off_all + b * sOff;
-  const double negl2 = 1e-30 * fro2_all[b];   // (1e-15 |M|_F)^2
-  const int nb = np / JW;
-  const int pr = blockIdx.x;
+  const double* Gt = Gt_all + b * sG;
+  const int nb = np / JW, pairs = nb / 2;
+  const int pr = blockIdx.x, ch = blockIdx.y;
   int p, q;
   circle_pair(nb, round, pr, p, q);
-
-  __shared__ double buf[4][JP][65];     // per-wave staging; reused for the Gram partials
-  __shared__ double H[JP][JP + 1];
-  __shared__ double W[JP][JP + 1];
+  __shared__ double sm[4 * 1024];          // staging [4][32][17], then the wave partials [4][1024]
   __shared__ int rowidx[JP];
-  __shared__ double wmax[4];
-  __shared__ int any;
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
   if (tid < JP) rowidx[tid] = (tid < JW) ? p * JW + tid : q * JW + (tid - JW);
   __syncthreads();
-
-  // ---- partial Gram matrices, wave wv takes row chunks wv, wv+4, ... ----
+  double* buf = sm + wv * (JP * 17);
   d4v acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0, 0, 0, 0};
-  for (int cb = 0; cb < m; cb += 256) {   // uniform trip count for every wave
-    const int c0 = cb + wv * 64;
-    for (int r = 0; r < JP; ++r) buf[wv][r][l] = (c0 + l < m) ? Gt[(long)rowidx[r] * m + c0 + l] : 0.0;
+  const int c0 = ch * JCH + wv * 64;
+  for (int sub = 0; sub < 4; ++sub) {      // 16 entries at a time, uniform for every wave
+    const int cs = c0 + sub * 16;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r = i * 4 + (l >> 4), c = l & 15;
+      buf[r * 17 + c] = (cs + c < m) ? Gt[(long)rowidx[r] * m + cs + c] : 0.0;
+    }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
       const int kc = kk * 4 + (l >> 4);
-      double a0 = buf[wv][l & 15][kc], a1 = buf[wv][16 + (l & 15)][kc];
+      const double a0 = buf[(l & 15) * 17 + kc], a1 = buf[(16 + (l & 15)) * 17 + kc];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, acc[1][0], 0, 0, 0);
@@ -157,29 +170,78 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* Gt_all, doubl
     }
     __syncthreads();
   }
+  // wave partials in the fragment order e = ((ti*2 + tj)*4 + r)*64 + lane
   for (int ti = 0; ti < 2; ++ti)
     for (int tj = 0; tj < 2; ++tj)
-      for (int r = 0; r < 4; ++r) buf[wv][ti * 16 + 4 * r + (l >> 4)][tj * 16 + (l & 15)] = acc[ti][tj][r];
+      for (int r = 0; r < 4; ++r) sm[wv * 1024 + ((ti * 2 + tj) * 4 + r) * 64 + l] = acc[ti][tj][r];
   __syncthreads();
-  for (int e = tid; e < JP * JP; e += 256) {
-    int i = e / JP, j = e % JP;
-    H[i][j] = buf[0][i][j] + buf[1][i][j] + buf[2][i][j] + buf[3][i][j];
+  double* out = part_all + (((long)b * pairs + pr) * nchunk + ch) * 1024;
+  for (int e = tid; e < 1024; e += 256) out[e] = (sm[e] + sm[1024 + e]) + (sm[2048 + e] + sm[3072 + e]);
+}
+
+// Jacobi rotation that zeroes the (a, c) entry of a symmetric 2 x 2 block:
+// new row a = c row_a - s row_c, new row c = s row_a + c row_c (same on
+// columns).  Below the threshold the identity is returned.
+__device__ inline void jacobi_rot(double haa, double hcc, double hac, double thr, double negl2, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (fabs(hac) > thr * sqrt(fmax(haa, negl2)) * sqrt(fmax(hcc, negl2))) {
+    const double zeta = (hcc - haa) / (2.0 * hac);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = c * t;
   }
+}
+
+// One workgroup (four wavefronts) per block pair.  Sums the Gram partials,
+// tests the pair and, unless it is converged, diagonalises the 32 x 32 Gram
+// matrix H by cyclic two-sided Jacobi in LDS: in each inner round the 32
+// indices form 16 disjoint pairs; thread (p, q) owns the 2 x 2 blocks of H
+// and of W (the accumulated rotations) at row pair p and column pair q,
+// computes both rotations itself and forms J_p^T H J_q and W J_q in
+// registers: one barrier after all reads, one after all writes.
+__global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_all, int nchunk, int np, int round,
+                                                           double tol, double* off_all, long sOff, double* W_all,
+                                                           int* rot_all, const int* done, int inner_sweeps,
+                                                           const double* fro2_all) {
+  const int b = blockIdx.y;
+  const int nb = np / JW, pairs = nb / 2;
+  const int pr = blockIdx.x;
+  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
+  int* rot = rot_all + (long)b * pairs + pr;
+  if (done[b]) {
+    if (tid == 0) *rot = 0;
+    return;
+  }
+  double* offv = off_all + b * sOff;
+  const double negl2 = 1e-26 * fro2_all[b];   // f^2 = (1e-13 |M|_F)^2
+  __shared__ double H[JP][JP + 1];
+  __shared__ double W[JP][JP + 1];
+  __shared__ double wmax[4];
+  __shared__ int any;
+  const double* part = part_all + ((long)b * pairs + pr) * nchunk * 1024;
+  for (int e = tid; e < 1024; e += 256) {
+    double a = 0.0;
+    for (int c = 0; c < nchunk; ++c) a += part[(long)c * 1024 + e];
+    const int lane = e & 63, r = (e >> 6) & 3, tt = e >> 8, ti = tt >> 1, tj = tt & 1;
+    H[ti * 16 + 4 * r + (lane >> 4)][tj * 16 + (lane & 15)] = a;
+  }
+  for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = (e / JP == e % JP) ? 1.0 : 0.0;
   __syncthreads();
 
   // ---- convergence measure of this pair (NaN-propagating max) ----
   double om = 0.0;
   for (int e = tid; e < JP * JP; e += 256) {
-    int i = e / JP, j = e % JP;
+    const int i = e / JP, j = e % JP;
     if (j > i) {
-      const double hii = fmax(H[i][i], 0.0), hjj = fmax(H[j][j], 0.0);
-      double v = (fmax(hii, hjj) <= negl2) ? 0.0 : fabs(H[i][j]) / (sqrt(hii) * sqrt(hjj) + 1e-300);
+      const double hii = fmax(H[i][i], negl2), hjj = fmax(H[j][j], negl2);
+      double v = fabs(H[i][j]) / (sqrt(hii) * sqrt(hjj) + 1e-300);
       if (H[i][j] != H[i][j] || H[i][i] != H[i][i] || H[j][j] != H[j][j]) v = NAN;
       om = (v != v || om != om) ? NAN : fmax(om, v);
     }
   }
   for (int w = 32; w > 0; w >>= 1) {
-    double o = __shfl_xor(om, w);
+    const double o = __shfl_xor(om, w);
     om = (o != o || om != om) ? NAN : fmax(om, o);
   }
   if (l == 0) wmax[wv] = om;
@@ -189,48 +251,27 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* Gt_all, doubl
     for (int k = 1; k < 4; ++k) a = (a != a || wmax[k] != wmax[k]) ? NAN : fmax(a, wmax[k]);
     om = a;
   }
-  if (tid == 0) offv[(long)round * (nb / 2) + pr] = om;
+  if (tid == 0) {
+    offv[(long)round * pairs + pr] = om;
+    *rot = (om > tol) ? 1 : 0;
+  }
   if (!(om > tol)) return;   // converged pair (or NaN: leave the data as is)
 
-  // ---- diagonalise H with cyclic two-sided Jacobi; W accumulates.  In each
-  // inner round the 32 indices form 16 disjoint pairs; thread (p, q) owns the
-  // 2 x 2 block of H at pairs p (rows) and q (columns) and the rows of W at
-  // pair p, computes both rotations itself, and forms J_p^T H J_q and W J_q
-  // in registers: one barrier after all reads, one after all writes. ----
-  for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = (e / JP == e % JP) ? 1.0 : 0.0;
-  const double rot_thr = 0.1 * tol;
+  const double thr = 0.1 * tol;
   const int pp = tid >> 4, qq = tid & 15;
   for (int sw = 0; sw < inner_sweeps; ++sw) {
-    __syncthreads();
     if (tid == 0) any = 0;
     __syncthreads();
     for (int rr = 0; rr < JP - 1; ++rr) {
       int ap, cp, aq, cq;
       circle_pair(JP, rr, pp, ap, cp);
       circle_pair(JP, rr, qq, aq, cq);
-      double c1 = 1.0, s1 = 0.0, c2 = 1.0, s2 = 0.0;
-      {
-        const double haa = H[ap][ap], hcc = H[cp][cp], hac = H[ap][cp];
-        if (fmax(haa, hcc) > negl2 && fabs(hac) > rot_thr * sqrt(fmax(haa, 0.0)) * sqrt(fmax(hcc, 0.0))) {
-          const double zeta = (hcc - haa) / (2.0 * hac);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c1 = 1.0 / sqrt(1.0 + t * t);
-          s1 = c1 * t;
-          if (qq == 0) any = 1;
-        }
-      }
-      {
-        const double haa = H[aq][aq], hcc = H[cq][cq], hac = H[aq][cq];
-        if (fmax(haa, hcc) > negl2 && fabs(hac) > rot_thr * sqrt(fmax(haa, 0.0)) * sqrt(fmax(hcc, 0.0))) {
-          const double zeta = (hcc - haa) / (2.0 * hac);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c2 = 1.0 / sqrt(1.0 + t * t);
-          s2 = c2 * t;
-        }
-      }
+      double c1, s1, c2, s2;
+      jacobi_rot(H[ap][ap], H[cp][cp], H[ap][cp], thr, negl2, c1, s1);
+      jacobi_rot(H[aq][aq], H[cq][cq], H[aq][cq], thr, negl2, c2, s2);
+      if (qq == 0 && s1 != 0.0) any = 1;
       const double h00 = H[ap][aq], h01 = H[ap][cq], h10 = H[cp][aq], h11 = H[cp][cq];
       const double w00 = W[ap][aq], w01 = W[ap][cq], w10 = W[cp][aq], w11 = W[cp][cq];
-      // rows: J_p^T
       const double r00 = c1 * h00 - s1 * h10, r01 = c1 * h01 - s1 * h11;
       const double r10 = s1 * h00 + c1 * h10, r11 = s1 * h01 + c1 * h11;
       __syncthreads();
@@ -245,50 +286,93 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* Gt_all, doubl
       __syncthreads();
     }
     if (!any) break;
+    __syncthreads();
   }
-  __syncthreads();
+  double* Wout = W_all + ((long)b * pairs + pr) * JP * JP;
+  for (int e = tid; e < JP * JP; e += 256) Wout[e] = W[e / JP][e % JP];
+}
 
-  // ---- rotate the 32 columns of G and of V: new = W^T old, per wave ----
-  for (int pass = 0; pass < 2; ++pass) {
-    double* X = pass == 0 ? Gt : Vt;
-    const int len = pass == 0 ? m : np;
-    for (int cb = 0; cb < len; cb += 256) {   // uniform trip count for every wave
-      const int c0 = cb + wv * 64;
-      for (int r = 0; r < JP; ++r) buf[wv][r][l] = (c0 + l < len) ? X[(long)rowidx[r] * len + c0 + l] : 0.0;
-      __syncthreads();
-      for (int ti = 0; ti < 2; ++ti)
-        for (int tc = 0; tc < 4; ++tc) {
-          d4v d = {0, 0, 0, 0};
+// new columns = old columns W for the rows of Gt (chunks 0 .. nchG-1, length
+// m) and of Vt (chunks nchG .., length np); each wave owns 64 entries of the
+// column length and reads all 32 columns there before writing them back.
+__global__ __launch_bounds__(256) void jacobi_rotate_kernel(double* Gt_all, double* Vt_all, int m, int np, int round,
+                                                            long sG, long sV, const double* W_all, const int* rot_all,
+                                                            int nchG, const int* done, unsigned long long* entries) {
+  const int b = blockIdx.z;
+  const int nb = np / JW, pairs = nb / 2;
+  const int pr = blockIdx.x;
+  if (done[b] || !rot_all[(long)b * pairs + pr]) return;
+  int p, q;
+  circle_pair(nb, round, pr, p, q);
+  __shared__ double Ws[JP][JP + 1];
+  __shared__ int rowidx[JP];
+  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
+  const double* Wg = W_all + ((long)b * pairs + pr) * JP * JP;
+  for (int e = tid; e < JP * JP; e += 256) Ws[e / JP][e % JP] = Wg[e];
+  if (tid < JP) rowidx[tid] = (tid < JW) ? p * JW + tid : q * JW + (tid - JW);
+  __syncthreads();
+  const bool isG = (int)blockIdx.y < nchG;
+  double* X = isG ? Gt_all + b * sG : Vt_all + b * sV;
+  const int len = isG ? m : np;
+  const int c0 = (isG ? blockIdx.y : blockIdx.y - nchG) * JCH + wv * 64;
+  if (tid == 0) {   // column-length entries rotated by this workgroup (statistics)
+    const int cb = (isG ? blockIdx.y : blockIdx.y - nchG) * JCH;
+    atomicAdd(entries, (unsigned long long)min(JCH, len - cb));
+  }
+  for (int tc = 0; tc < 4; ++tc) {
+    const int c = c0 + tc * 16 + (l & 15);
+    const bool in = c < len;
+    double old[8];
 #pragma unroll
-          for (int kk = 0; kk < 8; ++kk) {
-            const int j = kk * 4 + (l >> 4);
-            double a = W[j][ti * 16 + (l & 15)];      // (W^T)[i][j]
-            double bb = buf[wv][j][tc * 16 + (l & 15)];
-            d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, d, 0, 0, 0);
-          }
-          for (int r = 0; r < 4; ++r) {
-            const int i = ti * 16 + 4 * r + (l >> 4), c = c0 + tc * 16 + (l & 15);
-            if (c < len) X[(long)rowidx[i] * len + c] = d[r];
-          }
-        }
-      __syncthreads();
+    for (int kk = 0; kk < 8; ++kk) old[kk] = in ? X[(long)rowidx[kk * 4 + (l >> 4)] * len + c] : 0.0;
+    d4v d[2];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti) {
+      d[ti] = d4v{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const double a = Ws[kk * 4 + (l >> 4)][ti * 16 + (l & 15)];   // (W^T)[i][j]
+        d[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, old[kk], d[ti], 0, 0, 0);
+      }
+    }
+    if (in) {
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X[(long)rowidx[ti * 16 + 4 * r + (l >> 4)] * len + c] = d[ti][r];
     }
   }
 }
 
-// |M|_F^2 of every batch entry (one block each)
-__global__ void svd_fro2_kernel(const double* M, long nn, double* fro2) {
-  const double* x = M + (long)blockIdx.x * nn;
+// |M|_F^2 of every batch entry: FRO_BLOCKS blocks per entry write partial
+// sums, a second pass adds them in a fixed order.
+static constexpr int FRO_BLOCKS = 64;
+
+__global__ void svd_fro2_partial_kernel(const double* M, long nn, double* part) {
+  const int b = blockIdx.y;
+  const double* x = M + (long)b * nn;
   __shared__ double red[256];
   double a = 0.0;
-  for (long i = threadIdx.x; i < nn; i += blockDim.x) a += x[i] * x[i];
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < nn; i += 256L * FRO_BLOCKS) a += x[i] * x[i];
   red[threadIdx.x] = a;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) fro2[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) part[b * FRO_BLOCKS + blockIdx.x] = red[0];
+}
+
+__global__ void svd_fro2_final_kernel(const double* part, double* fro2) {
+  const int b = blockIdx.x;
+  __shared__ double red[FRO_BLOCKS];
+  red[threadIdx.x] = part[b * FRO_BLOCKS + threadIdx.x];
+  __syncthreads();
+  for (int w = FRO_BLOCKS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) fro2[b] = red[0];
 }
 
 __global__ void svd_check_kernel(const double* off_all, long sOff, double tol, int* done) {
@@ -371,12 +455,18 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
   int* rank = (int*)(w + L.offRank);
   int* done = (int*)(w + L.offDone);
   double* fro2 = (double*)(w + L.offFro);
-  hipLaunchKernelGGL(svd_fro2_kernel, dim3(batch), dim3(256), 0, s, M, (long)n * n, fro2);
+  double* part = (double*)(w + L.offPart);
+  double* Wr = (double*)(w + L.offW);
+  int* rot = (int*)(w + L.offRot);
+  unsigned long long* cnt = (unsigned long long*)(w + L.offCnt);
+  // the Gram partial buffer is free until the first round: it holds the norm partials
+  hipLaunchKernelGGL(svd_fro2_partial_kernel, dim3(FRO_BLOCKS, batch), dim3(256), 0, s, M, (long)n * n, part);
+  hipLaunchKernelGGL(svd_fro2_final_kernel, dim3(batch), dim3(FRO_BLOCKS), 0, s, (const double*)part, fro2);
   hipError_t err = hipSuccess;
   {
     long tot = (long)L.np * n + (long)L.np * L.np;
     int g = (int)std::min<long>((tot + 255) / 256, 8192);
-    hipLaunchKernelGGL(svd_init_kernel, dim3(g, batch), dim3(256), 0, s, M, V0, n, L.np, Gt, Vt, done, L.sG, L.sV);
+    hipLaunchKernelGGL(svd_init_kernel, dim3(g, batch), dim3(256), 0, s, M, V0, n, L.np, Gt, Vt, done, L.sG, L.sV, cnt);
     if (V0) {   // Gt[j][i] = sum_k V0[k][j] M[i][k]
       err = gemm_f64(s, true, true, n, n, n, 1.0, V0, n, (long)n * n, M, n, (long)n * n, 0.0, Gt, n, L.sG, batch);
       if (err != hipSuccess) return err;
@@ -385,28 +475,42 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
   int sweeps = 0;
   static const int inner = [] {
     const char* e = std::getenv("SPLITCTM_SVD_INNER");
-    int v = e ? std::atoi(e) : 2;
+    int v = e ? std::atoi(e) : 1;
     return v < 1 ? 1 : (v > 12 ? 12 : v);
   }();
   err = hipSuccess;
+  int running = batch;
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    KernelTimer* tm = kernel_timer();
-    // nominal work of one round: Gram matrix and rotation of G and V for every pair
-    const double round_work = (double)L.pairs * batch * 2.0 * JP * JP * (2.0 * n + L.np);
+    // algorithmic work of one round for the batch entries still running (the
+    // rotation's share is added from the device counter after the sweep)
+    const double gram_fl = (double)L.pairs * running * 2.0 * JP * JP * n;
+    const double gram_by = (double)L.pairs * running * 8.0 * (JP * (double)n + 1024.0 * L.nchG);
+    const double solve_by = (double)L.pairs * running * 8.0 * 1024.0 * (L.nchG + 1);
     for (int r = 0; r < L.rounds; ++r) {
-      if (tm) tm->begin(s, KC_JACOBI, round_work);
-      hipLaunchKernelGGL(jacobi_round_kernel, dim3(L.pairs, batch), dim3(256), 0, s, Gt, Vt, n, L.np, r, tol, off,
-                         done, L.sG, L.sV, L.sOff, inner, fro2);
-      if (tm) tm->end(s);
+      launch_timed(KC_JACOBI_GRAM, gram_fl, gram_by, jacobi_gram_kernel, dim3(L.pairs, L.nchG, batch), dim3(256), 0,
+                   s, (const double*)Gt, n, L.np, r, L.sG, part, L.nchG, (const int*)done);
+      launch_timed(KC_JACOBI_SOLVE, 0.0, solve_by, jacobi_solve_kernel, dim3(L.pairs, batch), dim3(256), 0, s,
+                   (const double*)part, L.nchG, L.np, r, tol, off, L.sOff, Wr, rot, (const int*)done, inner,
+                   (const double*)fro2);
+      launch_timed(KC_JACOBI_ROTATE, 0.0, 0.0, jacobi_rotate_kernel, dim3(L.pairs, L.nchG + L.nchV, batch), dim3(256),
+                   0, s, Gt, Vt, n, L.np, r, L.sG, L.sV, (const double*)Wr, (const int*)rot, L.nchG,
+                   (const int*)done, cnt);
     }
     hipLaunchKernelGGL(svd_check_kernel, dim3(batch), dim3(256), 0, s, off, L.sOff, tol, done);
     ++sweeps;
     err = hipMemcpyAsync(host_flags, done, sizeof(int) * batch, hipMemcpyDeviceToHost, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) return err;
-    bool all = true;
-    for (int b = 0; b < batch; ++b) all = all && host_flags[b];
-    if (all) break;
+    running = 0;
+    for (int b = 0; b < batch; ++b) running += host_flags[b] ? 0 : 1;
+    if (running == 0) break;
+  }
+  if (KernelTimer* tm = kernel_timer()) {   // exact work of the rotations that ran
+    unsigned long long e = 0;
+    err = hipMemcpyAsync(&e, cnt, sizeof(e), hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return err;
+    tm->add(KC_JACOBI_ROTATE, 2.0 * JP * JP * (double)e, 2.0 * JP * 8.0 * (double)e);
   }
   hipLaunchKernelGGL(svd_norms_kernel, dim3(n, batch), dim3(256), 0, s, Gt, n, L.sG, norms, L.np);
   hipLaunchKernelGGL(svd_rank_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, norms, n, L.np, rank);

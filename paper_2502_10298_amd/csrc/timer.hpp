@@ -1,29 +1,41 @@
-// HIP-event timing of selected kernel launches (diagnostics).  When a timer is
-// installed for the calling thread, every launch of a timed kernel class is
-// bracketed by two events on its stream; collect() (after the stream has been
-// synchronised) adds the elapsed times and the algorithmic work of the
-// launches to per-class totals.
+// Timing of selected kernel launches (diagnostics).  When a timer is
+// installed for the calling thread, every launch of a timed kernel class goes
+// through hipExtLaunchKernelGGL with a start and a stop event, which the
+// runtime records at the start and the end of that kernel's execution on its
+// stream; collect() (after the stream has been synchronised) adds the
+// elapsed times and the algorithmic work of the launches to per-class totals.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <vector>
 
 namespace sctm {
 
-enum KernelClass : int { KC_GEMM_F64 = 0, KC_GEMM_F32 = 1, KC_GEMM_BF16X3 = 2, KC_JACOBI = 3, KC_COUNT = 4 };
+enum KernelClass : int {
+  KC_GEMM_F64 = 0,
+  KC_GEMM_F32 = 1,
+  KC_GEMM_BF16X3 = 2,
+  KC_JACOBI_GRAM = 3,
+  KC_JACOBI_SOLVE = 4,
+  KC_JACOBI_ROTATE = 5,
+  KC_COUNT = 6
+};
 
 struct KernelTimer {
   struct Rec {
     int kind;
     hipEvent_t a, b;
-    double work;
+    double flops, bytes;
   };
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<Rec> pending;
-  double ms[KC_COUNT] = {0, 0, 0, 0};
-  double work[KC_COUNT] = {0, 0, 0, 0};
-  double launches[KC_COUNT] = {0, 0, 0, 0};
+  double ms[KC_COUNT] = {};
+  double flops[KC_COUNT] = {};
+  double bytes[KC_COUNT] = {};
+  double launches[KC_COUNT] = {};
 
   hipEvent_t next() {
     if (used == pool.size()) {
@@ -33,21 +45,24 @@ struct KernelTimer {
     }
     return pool[used++];
   }
-  void begin(hipStream_t s, int kind, double w) {
-    hipEvent_t a = next(), b = next();
-    if (!a || !b) return;
-    hipEventRecord(a, s);
-    pending.push_back({kind, a, b, w});
+  bool events(int kind, double f, double by, hipEvent_t& a, hipEvent_t& b) {
+    a = next();
+    b = next();
+    if (!a || !b) return false;
+    pending.push_back({kind, a, b, f, by});
+    return true;
   }
-  void end(hipStream_t s) {
-    if (!pending.empty()) hipEventRecord(pending.back().b, s);
+  void add(int kind, double f, double by) {
+    flops[kind] += f;
+    bytes[kind] += by;
   }
   void collect() {
     for (const Rec& r : pending) {
       float t = 0.f;
       if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
         ms[r.kind] += t;
-        work[r.kind] += r.work;
+        flops[r.kind] += r.flops;
+        bytes[r.kind] += r.bytes;
         launches[r.kind] += 1;
       }
     }
@@ -57,7 +72,7 @@ struct KernelTimer {
   void reset() {
     pending.clear();
     used = 0;
-    for (int k = 0; k < KC_COUNT; ++k) ms[k] = work[k] = launches[k] = 0;
+    for (int k = 0; k < KC_COUNT; ++k) ms[k] = flops[k] = bytes[k] = launches[k] = 0;
   }
   ~KernelTimer() {
     for (hipEvent_t e : pool) hipEventDestroy(e);
@@ -66,5 +81,18 @@ struct KernelTimer {
 
 // timer of the calling thread (nullptr: no timing)
 KernelTimer*& kernel_timer();
+
+// Launch `kernel`; when a timer is installed, with start / stop events of
+// class `kind` carrying the given algorithmic flops and bytes.
+template <typename F, typename... Args>
+inline void launch_timed(int kind, double flops, double bytes, F kernel, dim3 grid, dim3 block, uint32_t shmem,
+                         hipStream_t s, Args... args) {
+  KernelTimer* tm = kernel_timer();
+  hipEvent_t a, b;
+  if (tm && tm->events(kind, flops, bytes, a, b))
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, a, b, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+}
 
 }  // namespace sctm

@@ -42,6 +42,25 @@ def test_gemm(prec, tol, shape, tA, tB):
     assert err < tol, float(err)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("shape", [(64, 96, 20000), (130, 7, 8193), (1, 1, 65536), (200, 100, 1500)])
+@pytest.mark.parametrize("tA,tB", [(False, False), (True, False), (False, True), (True, True)])
+def test_gemm_split_k(prec, tol, shape, tA, tB):
+    """Long-K products with few output tiles run split over K (a ragged last
+    slice included) and must equal the plain product."""
+    M, N, K = shape
+    assert b.lib().ctm_debug_gemm_work_bytes(b.PREC[prec], M, N, K) > 0
+    _say("gemm split-k", prec, shape, tA, tB)
+    g = torch.Generator(device="cpu").manual_seed(M * 11 + N)
+    A = torch.randn((K, M) if tA else (M, K), generator=g, dtype=torch.float64)
+    B = torch.randn((N, K) if tB else (K, N), generator=g, dtype=torch.float64)
+    ref = (A.T if tA else A) @ (B.T if tB else B)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    C = b.debug_gemm(A.to(DEV, dt), B.to(DEV, dt), tA, tB, prec).double().cpu()
+    err = (C - ref).norm() / ref.norm()
+    assert err < tol, float(err)
+
+
 @pytest.mark.parametrize("n,batch", [(5, 1), (33, 2), (100, 3), (257, 1)])
 def test_jacobi_svd(n, batch):
     _say("svd", n, batch)
