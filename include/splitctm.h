@@ -137,6 +137,13 @@ size_t ctm_debug_gemm_work_bytes(int prec, int M, int N, int K);
 ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K, const void* A, const void* B,
                           void* C, void* work, void* hip_stream);
 size_t ctm_debug_svd_work_bytes(int n, int batch);
+/* ctm_debug_qr: Householder QR of batch tall matrices X (m x k, k <= m <=
+ * 4096) given transposed, Xt = X^T (k x m row-major, consecutive; overwritten
+ * by the reflectors and R).  R (k x k row-major, zero below the diagonal) and
+ * Qt = Q^T (k x m) receive the thin factors (either may be NULL); work =
+ * ctm_debug_qr_work_bytes bytes of device memory.  Synchronises the stream. */
+size_t ctm_debug_qr_work_bytes(int m, int k, int batch);
+ctm_status ctm_debug_qr(int m, int k, int batch, double* Xt, double* R, double* Qt, void* work, void* hip_stream);
 ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S, double* V, void* work,
                          int* sweeps, void* hip_stream);
 

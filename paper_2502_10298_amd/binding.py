@@ -22,7 +22,7 @@ INIT = {"identity": 0, "product": 1}
 
 EXPORTED = ("ctm_workspace_size", "ctm_init", "ctm_sweep", "ctm_projectors", "ctm_projectors_elems",
             "ctm_energy", "ctm_energy_grad", "ctm_env_elems", "ctm_env_export", "ctm_env_import",
-            "ctm_last_stats", "ctm_debug_gemm_work_bytes", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd",
+            "ctm_last_stats", "ctm_debug_gemm_work_bytes", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd", "ctm_debug_qr_work_bytes", "ctm_debug_qr",
             "ctm_kernel_timing_enable", "ctm_kernel_timing", "ctm_destroy", "ctm_strerror")
 KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "gemm_bf16x3": 2, "jacobi_gram": 3, "jacobi_solve": 4,
                   "jacobi_rotate": 5}
@@ -69,6 +69,8 @@ def lib() -> ctypes.CDLL:
         "ctm_debug_gemm": (I, [I, I, I, I, I, I, P, P, P, P, P]),
         "ctm_debug_svd_work_bytes": (S, [I, I]),
         "ctm_debug_svd": (I, [I, I, P, P, P, P, P, ctypes.POINTER(I), P]),
+        "ctm_debug_qr_work_bytes": (S, [I, I, I]),
+        "ctm_debug_qr": (I, [I, I, I, P, P, P, P, P]),
         "ctm_kernel_timing_enable": (I, [P, I]),
         "ctm_kernel_timing": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
         "ctm_destroy": (None, [P]),
@@ -268,6 +270,23 @@ def debug_svd(M, stream=None, max_sweeps=0):
     if st != CTM_OK:
         raise CtmError(st, "ctm_debug_svd")
     return U, S, V, sw.value
+
+
+def debug_qr(X, stream=None):
+    """Thin QR of a batch of tall matrices X [batch, m, k] (FP64, device):
+    returns (Q [batch, m, k], R [batch, k, k])."""
+    import torch
+    if X.dim() == 2:
+        X = X[None]
+    b, m, k = X.shape
+    Xt = X.transpose(1, 2).contiguous()
+    R = torch.empty((b, k, k), dtype=torch.float64, device=X.device)
+    Qt = torch.empty((b, k, m), dtype=torch.float64, device=X.device)
+    work = torch.empty(max(lib().ctm_debug_qr_work_bytes(m, k, b), 1), dtype=torch.uint8, device=X.device)
+    st = lib().ctm_debug_qr(m, k, b, _ptr(Xt), _ptr(R), _ptr(Qt), _ptr(work), _stream_ptr(torch, stream))
+    if st != CTM_OK:
+        raise CtmError(st, "ctm_debug_qr")
+    return Qt.transpose(1, 2), R
 
 
 class CtmEnergy:

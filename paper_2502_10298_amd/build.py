@@ -24,7 +24,7 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
-SOURCES = ["gemm.hip", "misc.hip", "svd.hip", "adj_kernels.hip", "engine.cpp", "ctm.cpp"]
+SOURCES = ["gemm.hip", "misc.hip", "svd.hip", "qr.hip", "adj_kernels.hip", "engine.cpp", "ctm.cpp"]
 
 
 def _compile(src: str) -> str:

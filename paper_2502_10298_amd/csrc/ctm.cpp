@@ -434,12 +434,15 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
                       {C1t[x], m.t[T1b], n.t[T1k], C2t[x], T4kt[x], T4bt[x], b, k, T2kt[x], T2bt[x]});
       Ten rB = E.ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
                       {T4kt[xp], T4bt[xp], C4t[xp], mp.t[T3b], np_.t[T3k], C3t[xp], bp, kp, T2kt[xp], T2bt[xp]});
-      Ten sT = E.ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
-                      {C1t[x], m.t[T1b], n.t[T1k], C2t[x], T4kt[x], k, T2kt[x]});
+      // the red upper half network factors through the (environment, D) bond
+      // (h, S): rho_T = X^T Z, so M_red has rank <= chi_E D
+      Ten sX = E.ncon("ae,eWh,aSYP->YPWhS", {C1t[x], m.t[T1b], T4kt[x]});
+      Ten sZ = E.ncon("hci,ij,QcSKr,jrJ->hSKQJ", {n.t[T1k], C2t[x], k, T2kt[x]});
+      Ten sT = E.contract("YPWhS,hSKQJ->YPWKQJ", sX, sZ);
       Ten sB = E.ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
                       {T4bt[x], C4t[x], m.t[T3b], n.t[T3k], C3t[x], b, T2bt[x]});
       rq.push_back({rT, rB, 2, true, ce, slot_of(c, dir, x, y, Ly, 4), spectra ? &sTH[x] : nullptr});
-      rq.push_back({sT, sB, 3, true, ci, slot_of(c, dir, x, y, Ly, 5), spectra ? &sR[x] : nullptr});
+      rq.push_back({sT, sB, 3, true, ci, slot_of(c, dir, x, y, Ly, 5), spectra ? &sR[x] : nullptr, sX, sZ});
     }
     auto out = E.projectors_batch(rq);
     for (int x = 0; x < Lx; ++x) {
@@ -1167,6 +1170,18 @@ ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K,
 }
 
 size_t ctm_debug_svd_work_bytes(int n, int batch) { return svd_work_bytes(n, batch); }
+
+size_t ctm_debug_qr_work_bytes(int m, int k, int batch) {
+  return (m >= k && k >= 1 && batch >= 1) ? qr_work_bytes(m, k, batch) : 0;
+}
+
+ctm_status ctm_debug_qr(int m, int k, int batch, double* Xt, double* R, double* Qt, void* work, void* stream) {
+  if (m < k || k < 1 || batch < 1 || m > 4096 || !Xt || !work) return CTM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = qr_f64(s, m, k, batch, Xt, R, Qt, work);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? CTM_OK : CTM_EDEVICE;
+}
 
 ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S, double* V, void* work,
                          int* sweeps, void* stream) {

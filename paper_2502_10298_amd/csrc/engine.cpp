@@ -599,18 +599,34 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
     ps[i].chi = q.chi;
     ps[i].rows = q.rows;
   }
+  // Route of every request: r0 > 0 when M = rho_B^T rho_T has rank <= r0 < n_b
+  // by construction (r0 = n_a, or the bond of a given factorisation of
+  // rho_T); M is then decomposed through an r0 x r0 core (Householder QR of
+  // the two r0 x n_b factors, Jacobi SVD of the core).  Else one-sided
+  // Jacobi on M itself.
+  std::vector<long> r0(nr, 0);
+  for (size_t i = 0; i < nr; ++i) {
+    const ProjReq& q = reqs[i];
+    long r = 0;
+    if (q.fX.p && q.fZ.p && q.rows) r = q.fZ.n() / ps[i].nb;
+    else if (ps[i].na < ps[i].nb) r = ps[i].na;
+    if (r > 0 && r < ps[i].nb && ps[i].nb <= 4096 && lowrank_svd) r0[i] = r;
+  }
   std::vector<char> handled(nr, 0);
   for (size_t g0 = 0; g0 < nr; ++g0) {
     if (handled[g0]) continue;
     std::vector<size_t> grp;
     for (size_t i = g0; i < nr; ++i)
-      if (!handled[i] && ps[i].nb == ps[g0].nb) {
+      if (!handled[i] && ps[i].nb == ps[g0].nb && r0[i] == r0[g0]) {
         grp.push_back(i);
         handled[i] = 1;
       }
     const long nb = ps[g0].nb;
+    const long rk = r0[g0];
     const int g = (int)grp.size();
-    Ten Mb = alloc(F64, {(long)g, nb, nb});
+    Ten Mb = alloc(F64, {(long)g, rk ? 1 : nb, rk ? 1 : nb});
+    Ten Xq;   // low-rank route: the factors L_j (entries 0..g-1), R_j (g..2g-1), r0 x n_b each
+    if (rk) Xq = alloc(F64, {2L * g, rk, nb});
     for (int j = 0; j < g; ++j) {
       const size_t i = grp[j];
       const ProjReq& q = reqs[i];
@@ -627,6 +643,33 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
           check(cast_f32_to_f64(s, q.rB.f32(), P.rB.f64(), q.rB.n()));
         }
       }
+      if (rk) {   // M = L^T R with L, R: r0 x n_b
+        const long offL = (long)j * rk * nb, offR = (long)(g + j) * rk * nb;
+        if (q.fX.p && q.fZ.p && q.rows && rk == q.fZ.n() / nb) {   // L = fX^T rho_B, R = fZ
+          size_t m2 = ar.mark();
+          Ten fX = alloc(F64, {na, rk});
+          if (!dry && ok()) {
+            if (q.fX.dt == F64) {
+              check(hipMemcpyAsync(fX.p, q.fX.p, q.fX.bytes(), hipMemcpyDeviceToDevice, s));
+              check(hipMemcpyAsync(Xq.f64() + offR, q.fZ.p, q.fZ.bytes(), hipMemcpyDeviceToDevice, s));
+            } else {
+              check(cast_f32_to_f64(s, q.fX.f32(), fX.f64(), q.fX.n()));
+              check(cast_f32_to_f64(s, q.fZ.f32(), Xq.f64() + offR, q.fZ.n()));
+            }
+          }
+          gemm(true, false, (int)rk, (int)nb, (int)na, 1.0, fX, 0, rk, P.rB, 0, nb, 0.0, Xq, offL, nb);
+          ar.release(m2);
+        } else if (q.rows) {   // L = rho_B, R = rho_T  (n_a x n_b)
+          if (!dry && ok()) {
+            check(hipMemcpyAsync(Xq.f64() + offL, P.rB.p, P.rB.bytes(), hipMemcpyDeviceToDevice, s));
+            check(hipMemcpyAsync(Xq.f64() + offR, P.rT.p, P.rT.bytes(), hipMemcpyDeviceToDevice, s));
+          }
+        } else {   // rho stored n_b x n_a: L = rho_B^T, R = rho_T^T
+          permute_into(P.rB, "ab->ba", view_of(*this, Xq, offL, {rk, nb}), false);
+          permute_into(P.rT, "ab->ba", view_of(*this, Xq, offR, {rk, nb}), false);
+        }
+        continue;
+      }
       const long off = (long)j * nb * nb;
       if (q.rows)   // M = rho_B^T rho_T  (b x b)
         gemm(true, false, (int)nb, (int)nb, (int)na, 1.0, P.rB, 0, nb, P.rT, 0, nb, 0.0, Mb, off, nb);
@@ -634,7 +677,7 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
         gemm(false, true, (int)nb, (int)nb, (int)na, 1.0, P.rB, 0, na, P.rT, 0, na, 0.0, Mb, off, nb);
     }
     Ten Ub = alloc(F64, {(long)g, nb, nb}), Sb = alloc(F64, {(long)g, nb}), Vb = alloc(F64, {(long)g, nb, nb});
-    bool warm_all = true;
+    bool warm_all = rk == 0;
     for (int j = 0; j < g; ++j) {
       int sl = reqs[grp[j]].slot;
       warm_all = warm_all && sl >= 0 && sl < (int)warm.size() && warm_valid[sl] && warm[sl].n() == nb * nb;
@@ -649,7 +692,21 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
             check(hipMemcpyAsync(V0.f64() + (long)j * nb * nb, warm[reqs[grp[j]].slot].p, sizeof(double) * nb * nb,
                                  hipMemcpyDeviceToDevice, s));
       }
-      void* work = ar.alloc(svd_work_bytes((int)nb, g));
+      void* work = rk ? nullptr : ar.alloc(svd_work_bytes((int)nb, g));
+      // low-rank route buffers
+      Ten Rq, Qq, Cq, Uq, Sq, Vq;
+      void* qwork = nullptr;
+      void* cwork = nullptr;
+      if (rk) {
+        Rq = alloc(F64, {2L * g, rk, rk});
+        Qq = alloc(F64, {2L * g, rk, nb});
+        Cq = alloc(F64, {(long)g, rk, rk});
+        Uq = alloc(F64, {(long)g, rk, rk});
+        Sq = alloc(F64, {(long)g, rk});
+        Vq = alloc(F64, {(long)g, rk, rk});
+        qwork = ar.alloc(qr_work_bytes((int)nb, (int)rk, 2 * g));
+        cwork = ar.alloc(svd_work_bytes((int)rk, g));
+      }
       // replay a recorded decomposition of the same matrices
       bool replayed = false;
       if (svdc_mode == 2 && svdc_slot >= 0) {
@@ -673,8 +730,28 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
         static const bool trace = getenv("SPLITCTM_SVD_TRACE") != nullptr;
         auto t0 = std::chrono::steady_clock::now();
         if (trace) check(hipStreamSynchronize(s));
-        check(svd_f64(s, (int)nb, g, Mb.f64(), Ub.f64(), Sb.f64(), Vb.f64(), work, svd_max_sweeps, svd_tol, host_flags,
-                      &sweeps, warm_all ? V0.f64() : nullptr));
+        if (rk) {
+          // Q_L R_L = L^T, Q_R R_R = R^T;  M = Q_L (R_L R_R^T) Q_R^T;  core = U' S V'^T
+          const long rr = rk * rk, rn = rk * nb, nn = nb * nb;
+          check(qr_f64(s, (int)nb, (int)rk, 2 * g, Xq.f64(), Rq.f64(), Qq.f64(), qwork));
+          check(gemm_f64(s, false, true, (int)rk, (int)rk, (int)rk, 1.0, Rq.f64(), rk, rr, Rq.f64() + g * rr, rk, rr,
+                         0.0, Cq.f64(), rk, rr, g));
+          check(svd_f64(s, (int)rk, g, Cq.f64(), Uq.f64(), Sq.f64(), Vq.f64(), cwork, svd_max_sweeps, svd_tol,
+                        host_flags, &sweeps, nullptr));
+          // U = Q_L U', V = Q_R V' in the first r0 columns; the rest (and S beyond r0) are zero
+          check(fill_f64(s, Ub.f64(), 0.0, g * nn));
+          check(fill_f64(s, Vb.f64(), 0.0, g * nn));
+          check(fill_f64(s, Sb.f64(), 0.0, g * nb));
+          check(gemm_f64(s, true, false, (int)nb, (int)rk, (int)rk, 1.0, Qq.f64(), nb, rn, Uq.f64(), rk, rr, 0.0,
+                         Ub.f64(), nb, nn, g));
+          check(gemm_f64(s, true, false, (int)nb, (int)rk, (int)rk, 1.0, Qq.f64() + g * rn, nb, rn, Vq.f64(), rk, rr,
+                         0.0, Vb.f64(), nb, nn, g));
+          check(hipMemcpy2DAsync(Sb.p, sizeof(double) * nb, Sq.p, sizeof(double) * rk, sizeof(double) * rk, g,
+                                 hipMemcpyDeviceToDevice, s));
+        } else {
+          check(svd_f64(s, (int)nb, g, Mb.f64(), Ub.f64(), Sb.f64(), Vb.f64(), work, svd_max_sweeps, svd_tol,
+                        host_flags, &sweeps, warm_all ? V0.f64() : nullptr));
+        }
         svd_sweeps_total += sweeps;
         svd_calls += 1;
         if (trace && ok()) {
@@ -685,8 +762,9 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
           int r = 0;
           for (long k = 0; k < nb; ++k) r += sv[k] > 1e-14 * sv[0];
           const int kc = std::min<long>(reqs[grp[0]].chi, nb) - 1;
-          fprintf(stderr, "[svd] n=%ld batch=%d warm=%d sweeps=%d %.1f ms rank=%d s_chi/s1=%.2e s_2chi/s1=%.2e\n", nb, g,
-                  (int)warm_all, sweeps, ms, r, sv[kc] / sv[0], sv[std::min<long>(2 * kc + 1, nb - 1)] / sv[0]);
+          fprintf(stderr, "[svd] n=%ld r0=%ld batch=%d warm=%d sweeps=%d %.1f ms rank=%d s_chi/s1=%.2e s_2chi/s1=%.2e\n",
+                  nb, rk, g, (int)warm_all, sweeps, ms, r, sv[kc] / sv[0],
+                  sv[std::min<long>(2 * kc + 1, nb - 1)] / sv[0]);
         }
       }
       if (!replayed && svdc_mode == 1 && svdc_slot >= 0) {   // record
@@ -710,7 +788,7 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
       }
       ar.release(mk);
     }
-    for (int j = 0; j < g; ++j) {
+    for (int j = 0; j < g && rk == 0; ++j) {
       int sl = reqs[grp[j]].slot;
       if (sl >= 0 && sl < (int)warm.size() && warm[sl].n() == nb * nb) {
         if (!dry && ok())

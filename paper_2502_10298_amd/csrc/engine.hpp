@@ -76,6 +76,10 @@ struct ProjReq {
   int chi;
   int slot;                          // warm-start slot (-1: cold start)
   std::vector<double>* spectrum_out;
+  // optional factorisation rho_T = fX^T fZ through a bond of dimension r0
+  // (fX: a-legs x r0, fZ: r0 x b-legs; rows layout only): M = (fX^T rho_B)^T fZ
+  // then has rank <= r0 and is decomposed through that core.
+  Ten fX, fZ;
 };
 
 struct PlanStep {
@@ -152,6 +156,7 @@ struct Engine {
   std::vector<Ten> warm;
   std::vector<char> warm_valid;
   long svd_calls = 0;
+  bool lowrank_svd = true;           // decompose rank-limited M through its r0 x r0 core
   // Record / replay of projector SVDs per move of a checkpoint block: the
   // recomputation of a move rebuilds bit-identical matrices M, so the U, S, V
   // recorded when the move first ran are reused instead of recomputed.

@@ -73,6 +73,11 @@ hipError_t normalize_adjoint_f32(hipStream_t s, const float* y, const float* yba
 // Columns of U whose singular value is zero are left zero.
 // work must hold svd_work_bytes(n, batch) bytes.
 size_t svd_work_bytes(int n, int batch);
+// Householder QR of batch tall matrices X (m x k, m >= k, m <= 4096) given as
+// Xt = X^T (k x m row-major, overwritten).  R: k x k upper triangular
+// (row-major), Qt = Q^T (k x m); either may be null.
+size_t qr_work_bytes(int m, int k, int batch);
+hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R, double* Qt, void* work);
 // host_flags: host buffer of >= batch ints (convergence flags are read back
 // once per sweep; the stream is synchronised at that point).
 // V0 (optional, batch of n x n): start the iteration from G = M V0, V = V0

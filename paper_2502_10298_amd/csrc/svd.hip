@@ -32,7 +32,7 @@ static inline int padded(int n) { return ((n + JP - 1) / JP) * JP; }
 struct SvdLayout {
   int np, nb, pairs, rounds, nchG, nchV;
   long sG, sV, sOff;
-  size_t offG, offV, offOff, offNorm, offRank, offDone, offFro, offPart, offW, offRot, offCnt, total;
+  size_t offG, offV, offG2, offV2, offOff, offNorm, offRank, offDone, offFro, offPart, offW, offRot, offCnt, total;
 };
 
 static SvdLayout layout(int n, int batch) {
@@ -54,6 +54,8 @@ static SvdLayout layout(int n, int batch) {
   };
   L.offG = take(sizeof(double) * L.sG * batch);
   L.offV = take(sizeof(double) * L.sV * batch);
+  L.offG2 = take(sizeof(double) * L.sG * batch);
+  L.offV2 = take(sizeof(double) * L.sV * batch);
   L.offOff = take(sizeof(double) * L.sOff * batch);
   L.offNorm = take(sizeof(double) * (size_t)L.np * batch);
   L.offRank = take(sizeof(int) * (size_t)L.np * batch);
@@ -407,6 +409,17 @@ __global__ void svd_norms_kernel(const double* Gt_all, int n, long sG, double* n
   if (threadIdx.x == 0) norms_all[(long)b * np + j] = sqrt(red[0]);
 }
 
+// Rows of X (length len, np rows per batch entry) moved to the positions of
+// the descending column-norm order (rows >= n keep their place).
+__global__ void svd_permute_rows_kernel(const double* Xin_all, double* Xout_all, const int* rank_all, int n, int np,
+                                        int len, long sX) {
+  const int j = blockIdx.x, b = blockIdx.y;
+  const int dst = (j < n) ? rank_all[(long)b * np + j] : j;
+  const double* src = Xin_all + b * sX + (long)j * len;
+  double* out = Xout_all + b * sX + (long)dst * len;
+  for (int i = threadIdx.x; i < len; i += blockDim.x) out[i] = src[i];
+}
+
 __global__ void svd_rank_kernel(const double* norms_all, int n, int np, int* rank_all) {
   const int b = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -450,6 +463,8 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
   char* w = (char*)work;
   double* Gt = (double*)(w + L.offG);
   double* Vt = (double*)(w + L.offV);
+  double* Gt2 = (double*)(w + L.offG2);
+  double* Vt2 = (double*)(w + L.offV2);
   double* off = (double*)(w + L.offOff);
   double* norms = (double*)(w + L.offNorm);
   int* rank = (int*)(w + L.offRank);
@@ -481,6 +496,18 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
   err = hipSuccess;
   int running = batch;
   for (int sw = 0; sw < max_sweeps; ++sw) {
+    // columns in descending norm order before every sweep (the large ones
+    // meet first in the tournament, which cuts the sweep count of graded
+    // spectra); V's columns follow the same permutation
+    hipLaunchKernelGGL(svd_norms_kernel, dim3(n, batch), dim3(256), 0, s, (const double*)Gt, n, L.sG, norms, L.np);
+    hipLaunchKernelGGL(svd_rank_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, (const double*)norms, n, L.np,
+                       rank);
+    hipLaunchKernelGGL(svd_permute_rows_kernel, dim3(L.np, batch), dim3(256), 0, s, (const double*)Gt, Gt2,
+                       (const int*)rank, n, L.np, n, L.sG);
+    hipLaunchKernelGGL(svd_permute_rows_kernel, dim3(L.np, batch), dim3(256), 0, s, (const double*)Vt, Vt2,
+                       (const int*)rank, n, L.np, L.np, L.sV);
+    std::swap(Gt, Gt2);
+    std::swap(Vt, Vt2);
     // algorithmic work of one round for the batch entries still running (the
     // rotation's share is added from the device counter after the sweep)
     const double gram_fl = (double)L.pairs * running * 2.0 * JP * JP * n;

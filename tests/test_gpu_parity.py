@@ -88,6 +88,30 @@ def test_jacobi_svd(n, batch):
     assert sweeps < 60
 
 
+@pytest.mark.parametrize("m,k,batch", [(40, 17, 1), (300, 150, 3), (2048, 1024, 2), (3200, 160, 1), (64, 64, 2)])
+def test_householder_qr(m, k, batch):
+    """X = Q R with Q orthonormal and R upper triangular, to working accuracy,
+    on graded and rank-deficient inputs (panels of 16, 8 and 4 columns)."""
+    _say("qr", m, k, batch)
+    g = torch.Generator().manual_seed(m + k)
+    X = torch.randn(batch, m, k, generator=g, dtype=torch.float64)
+    X[0] = X[0] * torch.logspace(0, -10, k, dtype=torch.float64)[None, :]      # graded columns
+    if batch > 1:
+        X[1, :, k // 2:] = X[1, :, : k - k // 2] @ torch.randn(k - k // 2, k - k // 2, generator=g,
+                                                             dtype=torch.float64)   # rank k - k // 2
+    Q, R = b.debug_qr(X.to(DEV))
+    Q, R = Q.cpu(), R.cpu()
+    for i in range(batch):
+        assert torch.allclose(Q[i].T @ Q[i], torch.eye(k, dtype=torch.float64), atol=1e-13 * math.sqrt(m))
+        assert (Q[i] @ R[i] - X[i]).norm() <= 1e-14 * math.sqrt(m * k) * X[i].norm()
+        assert torch.equal(torch.triu(R[i]), R[i])
+        # |R| diagonal equals the oracle-independent Householder result up to signs
+        ref = torch.linalg.qr(X[i])[1]
+        if i != 1:
+            assert torch.allclose(R[i].diagonal().abs(), ref.diagonal().abs(), rtol=1e-8,
+                                  atol=1e-13 * float(X[i].norm()))
+
+
 # ---------------------------------------------------------------------------
 # whole path, FP64, against the oracle
 # ---------------------------------------------------------------------------
