@@ -53,7 +53,6 @@ struct ctm_ctx {
   size_t transient_mark = 0;
   int host_flags[256];
   bool have_spec = false;
-  bool warm_start = true;
   double last_flops = 0, last_sweeps = 0;
   bool timing = false;     // HIP-event timing of the GEMM and Jacobi launches
   KernelTimer timer;
@@ -339,14 +338,6 @@ struct Column {
 // One column of a left move (Sec. II B, App. A).  Writes the new C1, T4k,
 // T4b, C4 of column y+1 into `env` unless `want_row` >= 0, in which case only
 // the projectors of that row / cut are kept in `col` (env untouched).
-// Warm-start slot of projector `color` (0 green, 1 green', 2 yellow,
-// 3 yellow', 4 teal, 5 red) of row x, column y in the frame of move `dir`.
-int slot_of(const ctm_ctx& c, int dir, int x, int y, int Ly, int color) {
-  if (dir < 0 || !c.warm_start) return -1;
-  const int nsite = c.Lx * c.Ly;
-  return ((dir * nsite + x * Ly + y) * 6) + color;
-}
-
 void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int want_row, int dir) {
   Engine& E = c.E;
   const int Lx = env.Lx, Ly = env.Ly, ce = c.chiE, ci = c.chiI;
@@ -385,10 +376,10 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
     std::vector<ProjReq> rq;
     for (int x = 0; x < Lx; ++x) {
       const int xp = (x + 1) % Lx;
-      rq.push_back({gT[x], gB[xp], 2, true, ce, slot_of(c, dir, x, y, Ly, 0), spectra ? &sG[x] : nullptr});
-      rq.push_back({gT2[x], gB2[xp], 2, false, ce, slot_of(c, dir, x, y, Ly, 1), nullptr});
-      rq.push_back({yT[x], yB[x], 2, true, ci, slot_of(c, dir, x, y, Ly, 2), spectra ? &sY[x] : nullptr});
-      rq.push_back({yT2[x], yB2[x], 2, false, ci, slot_of(c, dir, x, y, Ly, 3), nullptr});
+      rq.push_back({gT[x], gB[xp], 2, true, ce, spectra ? &sG[x] : nullptr});
+      rq.push_back({gT2[x], gB2[xp], 2, false, ce, nullptr});
+      rq.push_back({yT[x], yB[x], 2, true, ci, spectra ? &sY[x] : nullptr});
+      rq.push_back({yT2[x], yB2[x], 2, false, ci, nullptr});
     }
     auto out = E.projectors_batch(rq);
     for (int x = 0; x < Lx; ++x) {
@@ -441,8 +432,8 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
       Ten sT = E.contract("YPWhS,hSKQJ->YPWKQJ", sX, sZ);
       Ten sB = E.ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
                       {T4bt[x], C4t[x], m.t[T3b], n.t[T3k], C3t[x], b, T2bt[x]});
-      rq.push_back({rT, rB, 2, true, ce, slot_of(c, dir, x, y, Ly, 4), spectra ? &sTH[x] : nullptr});
-      rq.push_back({sT, sB, 3, true, ci, slot_of(c, dir, x, y, Ly, 5), spectra ? &sR[x] : nullptr, sX, sZ});
+      rq.push_back({rT, rB, 2, true, ce, spectra ? &sTH[x] : nullptr});
+      rq.push_back({sT, sB, 3, true, ci, spectra ? &sR[x] : nullptr, sX, sZ});
     }
     auto out = E.projectors_batch(rq);
     for (int x = 0; x < Lx; ++x) {
@@ -605,19 +596,6 @@ void init_persistent(ctm_ctx* c, const double* A_dev, const double* bvec) {
   c->h64 = E.alloc(F64, {(long)c->p * c->p * c->p * c->p});
   Ten part = E.alloc(F64, {(long)reduce_partials()});
   E.partial = part.f64();
-  // warm-start right singular vectors of every projector slot
-  {
-    const long n1 = (long)c->chiE * c->D, n2 = (long)c->p * c->D * c->chiI;
-    const int nslot = 4 * c->Lx * c->Ly * 6;
-    E.warm.assign(nslot, Ten());
-    E.warm_valid.assign(nslot, 0);
-    if (c->warm_start)
-      for (int sl = 0; sl < nslot; ++sl) {
-        const int color = sl % 6;
-        const long nb = (color == 2 || color == 3 || color == 5) ? n2 : n1;
-        E.warm[sl] = E.alloc(F64, {nb, nb});
-      }
-  }
   if (!E.dry && E.ok()) {
     E.check(hipMemcpyAsync(c->A64.p, A_dev, c->A64.bytes(), hipMemcpyDeviceToDevice, E.s));
     if (E.cdt == F32) E.check(cast_f64_to_f32(E.s, c->A64.f64(), c->Aflat.f32(), c->A64.n()));
@@ -1138,7 +1116,6 @@ ctm_status ctm_env_import(ctm_ctx* c, const double* env_dev) {
   E.check(hipMemcpyAsync(c->start_blk.p, c->cur_blk.p, c->cur_blk.bytes(), hipMemcpyDeviceToDevice, E.s));
   E.check(hipStreamSynchronize(E.s));
   c->have_spec = false;
-  std::fill(E.warm_valid.begin(), E.warm_valid.end(), 0);
   return (ctm_status)status_from_engine(E);
 }
 
@@ -1169,7 +1146,7 @@ ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K,
   return e == hipSuccess ? CTM_OK : CTM_EDEVICE;
 }
 
-size_t ctm_debug_svd_work_bytes(int n, int batch) { return svd_work_bytes(n, batch); }
+size_t ctm_debug_svd_work_bytes(int n, int batch) { return svd_precond_work_bytes(n, batch); }
 
 size_t ctm_debug_qr_work_bytes(int m, int k, int batch) {
   return (m >= k && k >= 1 && batch >= 1) ? qr_work_bytes(m, k, batch) : 0;
@@ -1189,7 +1166,7 @@ ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S
   hipStream_t s = (hipStream_t)stream;
   int flags[256];
   const int max_sweeps = (sweeps && *sweeps > 0) ? *sweeps : 60;
-  hipError_t e = svd_f64(s, n, batch, M, U, S, V, work, max_sweeps, 0.0, flags, sweeps);
+  hipError_t e = svd_precond_f64(s, n, batch, M, U, S, V, work, max_sweeps, 0.0, flags, sweeps);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e == hipSuccess ? CTM_OK : CTM_EDEVICE;
 }

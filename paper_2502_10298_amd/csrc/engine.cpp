@@ -557,7 +557,7 @@ Ten Engine::ncon(const std::string& spec, const std::vector<Ten>& ops) {
 // ---------------------------------------------------------------------------
 std::vector<Ten> Engine::projectors(const Ten& rT, const Ten& rB, int n_a, bool rows, int chi,
                                     std::vector<double>* spectrum_out) {
-  ProjReq q{rT, rB, n_a, rows, chi, -1, spectrum_out};
+  ProjReq q{rT, rB, n_a, rows, chi, spectrum_out};
   return projectors_batch({q})[0];
 }
 
@@ -571,10 +571,10 @@ static Ten view_of(Engine& E, const Ten& base, long off_elems, const std::vector
   return t;
 }
 
-// Projector pairs for several cuts at once.  Requests whose matrix M has the
-// same size share one batched Jacobi SVD (one launch per round for all of
-// them); a request with a warm-start slot starts its SVD from the right
-// singular vectors that slot kept from the previous call.
+// Projector pairs for several cuts at once.  All matrices handed to the
+// Jacobi SVD that have the same size (the matrices M of the full-rank
+// requests and the cores of the rank-limited ones) share one batched SVD:
+// one launch per round for all of them.
 std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq>& reqs) {
   const size_t nr = reqs.size();
   std::vector<std::vector<Ten>> result(nr);
@@ -612,200 +612,224 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
     else if (ps[i].na < ps[i].nb) r = ps[i].na;
     if (r > 0 && r < ps[i].nb && ps[i].nb <= 4096 && lowrank_svd) r0[i] = r;
   }
-  std::vector<char> handled(nr, 0);
-  for (size_t g0 = 0; g0 < nr; ++g0) {
-    if (handled[g0]) continue;
-    std::vector<size_t> grp;
-    for (size_t i = g0; i < nr; ++i)
-      if (!handled[i] && ps[i].nb == ps[g0].nb && r0[i] == r0[g0]) {
-        grp.push_back(i);
-        handled[i] = 1;
+  // groups of equal (n_b, r0), in request order
+  struct Group {
+    std::vector<size_t> idx;
+    long nb = 0, rk = 0, n = 0;   // n: size of the matrices handed to the Jacobi SVD
+    Ten Ub, Sb, Vb;               // n_b x n_b factors of M
+    bool replayed = false;
+    long job0 = 0;                // first entry in the Jacobi batch of size n
+    Ten Xq, Rq, Qq;               // low-rank route: factors, R's and Q^T's
+  };
+  std::vector<Group> groups;
+  {
+    std::vector<char> handled(nr, 0);
+    for (size_t g0 = 0; g0 < nr; ++g0) {
+      if (handled[g0]) continue;
+      Group G;
+      for (size_t i = g0; i < nr; ++i)
+        if (!handled[i] && ps[i].nb == ps[g0].nb && r0[i] == r0[g0]) {
+          G.idx.push_back(i);
+          handled[i] = 1;
+        }
+      G.nb = ps[g0].nb;
+      G.rk = r0[g0];
+      G.n = G.rk ? G.rk : G.nb;
+      groups.push_back(std::move(G));
+    }
+  }
+  // FP64 copies of the half networks (kept for the projector formation and the reverse pass)
+  for (size_t i = 0; i < nr; ++i) {
+    const ProjReq& q = reqs[i];
+    ProjSaved& P = ps[i];
+    const long na = P.na, nb = P.nb;
+    P.rT = alloc(F64, {q.rows ? na : nb, q.rows ? nb : na});
+    P.rB = alloc(F64, {q.rows ? na : nb, q.rows ? nb : na});
+    if (!dry && ok()) {
+      if (q.rT.dt == F64) {
+        check(hipMemcpyAsync(P.rT.p, q.rT.p, q.rT.bytes(), hipMemcpyDeviceToDevice, s));
+        check(hipMemcpyAsync(P.rB.p, q.rB.p, q.rB.bytes(), hipMemcpyDeviceToDevice, s));
+      } else {
+        check(cast_f32_to_f64(s, q.rT.f32(), P.rT.f64(), q.rT.n()));
+        check(cast_f32_to_f64(s, q.rB.f32(), P.rB.f64(), q.rB.n()));
       }
-    const long nb = ps[g0].nb;
-    const long rk = r0[g0];
-    const int g = (int)grp.size();
-    Ten Mb = alloc(F64, {(long)g, rk ? 1 : nb, rk ? 1 : nb});
-    Ten Xq;   // low-rank route: the factors L_j (entries 0..g-1), R_j (g..2g-1), r0 x n_b each
-    if (rk) Xq = alloc(F64, {2L * g, rk, nb});
-    for (int j = 0; j < g; ++j) {
-      const size_t i = grp[j];
-      const ProjReq& q = reqs[i];
-      ProjSaved& P = ps[i];
-      const long na = P.na;
-      P.rT = alloc(F64, {q.rows ? na : nb, q.rows ? nb : na});
-      P.rB = alloc(F64, {q.rows ? na : nb, q.rows ? nb : na});
+    }
+  }
+  // replay of recorded decompositions (same group order as when recorded)
+  for (Group& G : groups) {
+    const long nb = G.nb, g = (long)G.idx.size();
+    if (svdc_mode != 2 || svdc_slot < 0) continue;
+    SvdCacheSlot& sl = svdc_slots[svdc_slot];
+    if (sl.valid && svdc_cursor < sl.off.size() && sl.nb[svdc_cursor] == nb && sl.g[svdc_cursor] == g) {
+      G.Ub = alloc(F64, {g, nb, nb});
+      G.Sb = alloc(F64, {g, nb});
+      G.Vb = alloc(F64, {g, nb, nb});
       if (!dry && ok()) {
-        if (q.rT.dt == F64) {
-          check(hipMemcpyAsync(P.rT.p, q.rT.p, q.rT.bytes(), hipMemcpyDeviceToDevice, s));
-          check(hipMemcpyAsync(P.rB.p, q.rB.p, q.rB.bytes(), hipMemcpyDeviceToDevice, s));
-        } else {
-          check(cast_f32_to_f64(s, q.rT.f32(), P.rT.f64(), q.rT.n()));
-          check(cast_f32_to_f64(s, q.rB.f32(), P.rB.f64(), q.rB.n()));
-        }
+        const double* src = svdc_buf.f64() + (long)svdc_slot * svdc_per_slot + sl.off[svdc_cursor];
+        const long un = g * nb * nb, sn = g * nb;
+        check(hipMemcpyAsync(G.Ub.p, src, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
+        check(hipMemcpyAsync(G.Sb.p, src + un, sizeof(double) * sn, hipMemcpyDeviceToDevice, s));
+        check(hipMemcpyAsync(G.Vb.p, src + un + sn, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
       }
-      if (rk) {   // M = L^T R with L, R: r0 x n_b
-        const long offL = (long)j * rk * nb, offR = (long)(g + j) * rk * nb;
-        if (q.fX.p && q.fZ.p && q.rows && rk == q.fZ.n() / nb) {   // L = fX^T rho_B, R = fZ
-          size_t m2 = ar.mark();
-          Ten fX = alloc(F64, {na, rk});
-          if (!dry && ok()) {
-            if (q.fX.dt == F64) {
-              check(hipMemcpyAsync(fX.p, q.fX.p, q.fX.bytes(), hipMemcpyDeviceToDevice, s));
-              check(hipMemcpyAsync(Xq.f64() + offR, q.fZ.p, q.fZ.bytes(), hipMemcpyDeviceToDevice, s));
-            } else {
-              check(cast_f32_to_f64(s, q.fX.f32(), fX.f64(), q.fX.n()));
-              check(cast_f32_to_f64(s, q.fZ.f32(), Xq.f64() + offR, q.fZ.n()));
-            }
-          }
-          gemm(true, false, (int)rk, (int)nb, (int)na, 1.0, fX, 0, rk, P.rB, 0, nb, 0.0, Xq, offL, nb);
-          ar.release(m2);
-        } else if (q.rows) {   // L = rho_B, R = rho_T  (n_a x n_b)
-          if (!dry && ok()) {
-            check(hipMemcpyAsync(Xq.f64() + offL, P.rB.p, P.rB.bytes(), hipMemcpyDeviceToDevice, s));
-            check(hipMemcpyAsync(Xq.f64() + offR, P.rT.p, P.rT.bytes(), hipMemcpyDeviceToDevice, s));
-          }
-        } else {   // rho stored n_b x n_a: L = rho_B^T, R = rho_T^T
-          permute_into(P.rB, "ab->ba", view_of(*this, Xq, offL, {rk, nb}), false);
-          permute_into(P.rT, "ab->ba", view_of(*this, Xq, offR, {rk, nb}), false);
-        }
-        continue;
-      }
-      const long off = (long)j * nb * nb;
-      if (q.rows)   // M = rho_B^T rho_T  (b x b)
-        gemm(true, false, (int)nb, (int)nb, (int)na, 1.0, P.rB, 0, nb, P.rT, 0, nb, 0.0, Mb, off, nb);
-      else          // M = rho_B rho_T^T
-        gemm(false, true, (int)nb, (int)nb, (int)na, 1.0, P.rB, 0, na, P.rT, 0, na, 0.0, Mb, off, nb);
+      ++svdc_cursor;
+      G.replayed = true;
+    } else {
+      sl.valid = false;   // out of step with the recording: recompute from here on
     }
-    Ten Ub = alloc(F64, {(long)g, nb, nb}), Sb = alloc(F64, {(long)g, nb}), Vb = alloc(F64, {(long)g, nb, nb});
-    bool warm_all = rk == 0;
-    for (int j = 0; j < g; ++j) {
-      int sl = reqs[grp[j]].slot;
-      warm_all = warm_all && sl >= 0 && sl < (int)warm.size() && warm_valid[sl] && warm[sl].n() == nb * nb;
+  }
+  // one Jacobi batch per matrix size over all groups still to decompose
+  std::vector<long> sizes;
+  std::unordered_map<long, long> jobs;       // n -> batch entries
+  for (Group& G : groups) {
+    if (G.replayed) continue;
+    if (!jobs.count(G.n)) sizes.push_back(G.n);
+    G.job0 = jobs[G.n];
+    jobs[G.n] += (long)G.idx.size();
+  }
+  std::unordered_map<long, Ten> jU, jS, jV;   // Jacobi outputs (persist: views are kept for the reverse pass)
+  for (long n : sizes) {
+    jU[n] = alloc(F64, {jobs[n], n, n});
+    jS[n] = alloc(F64, {jobs[n], n});
+    jV[n] = alloc(F64, {jobs[n], n, n});
+  }
+  for (Group& G : groups) {
+    if (G.replayed) continue;
+    const long nb = G.nb, g = (long)G.idx.size();
+    if (G.rk) {   // factors of M (n_b x n_b) beyond the core
+      G.Ub = alloc(F64, {g, nb, nb});
+      G.Sb = alloc(F64, {g, nb});
+      G.Vb = alloc(F64, {g, nb, nb});
+    } else {      // the Jacobi outputs are the factors themselves
+      G.Ub = view_of(*this, jU[G.n], G.job0 * nb * nb, {g, nb, nb});
+      G.Sb = view_of(*this, jS[G.n], G.job0 * nb, {g, nb});
+      G.Vb = view_of(*this, jV[G.n], G.job0 * nb * nb, {g, nb, nb});
     }
-    {
-      size_t mk = ar.mark();
-      Ten V0;
-      if (warm_all) {
-        V0 = alloc(F64, {(long)g, nb, nb});
-        if (!dry && ok())
-          for (int j = 0; j < g; ++j)
-            check(hipMemcpyAsync(V0.f64() + (long)j * nb * nb, warm[reqs[grp[j]].slot].p, sizeof(double) * nb * nb,
-                                 hipMemcpyDeviceToDevice, s));
+  }
+  size_t mk = ar.mark();   // transient from here: Jacobi inputs, QR buffers, workspaces
+  std::unordered_map<long, Ten> jM;
+  for (long n : sizes) jM[n] = alloc(F64, {jobs[n], n, n});
+  for (Group& G : groups) {
+    if (G.replayed) continue;
+    const long nb = G.nb, rk = G.rk, g = (long)G.idx.size();
+    if (!rk) {   // M = rho_B^T rho_T straight into the Jacobi batch
+      for (long j = 0; j < g; ++j) {
+        const ProjSaved& P = ps[G.idx[j]];
+        const long na = P.na, off = (G.job0 + j) * nb * nb;
+        if (P.rows)
+          gemm(true, false, (int)nb, (int)nb, (int)na, 1.0, P.rB, 0, nb, P.rT, 0, nb, 0.0, jM[nb], off, nb);
+        else
+          gemm(false, true, (int)nb, (int)nb, (int)na, 1.0, P.rB, 0, na, P.rT, 0, na, 0.0, jM[nb], off, nb);
       }
-      void* work = rk ? nullptr : ar.alloc(svd_work_bytes((int)nb, g));
-      // low-rank route buffers
-      Ten Rq, Qq, Cq, Uq, Sq, Vq;
-      void* qwork = nullptr;
-      void* cwork = nullptr;
-      if (rk) {
-        Rq = alloc(F64, {2L * g, rk, rk});
-        Qq = alloc(F64, {2L * g, rk, nb});
-        Cq = alloc(F64, {(long)g, rk, rk});
-        Uq = alloc(F64, {(long)g, rk, rk});
-        Sq = alloc(F64, {(long)g, rk});
-        Vq = alloc(F64, {(long)g, rk, rk});
-        qwork = ar.alloc(qr_work_bytes((int)nb, (int)rk, 2 * g));
-        cwork = ar.alloc(svd_work_bytes((int)rk, g));
-      }
-      // replay a recorded decomposition of the same matrices
-      bool replayed = false;
-      if (svdc_mode == 2 && svdc_slot >= 0) {
-        SvdCacheSlot& sl = svdc_slots[svdc_slot];
-        if (sl.valid && svdc_cursor < sl.off.size() && sl.nb[svdc_cursor] == nb && sl.g[svdc_cursor] == g) {
-          if (!dry && ok()) {
-            const double* src = svdc_buf.f64() + (long)svdc_slot * svdc_per_slot + sl.off[svdc_cursor];
-            const long un = (long)g * nb * nb, sn = (long)g * nb;
-            check(hipMemcpyAsync(Ub.p, src, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
-            check(hipMemcpyAsync(Sb.p, src + un, sizeof(double) * sn, hipMemcpyDeviceToDevice, s));
-            check(hipMemcpyAsync(Vb.p, src + un + sn, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
-          }
-          ++svdc_cursor;
-          replayed = true;
-        } else {
-          sl.valid = false;   // out of step with the recording: recompute from here on
-        }
-      }
-      if (!replayed && !dry && ok()) {
-        int sweeps = 0;
-        static const bool trace = getenv("SPLITCTM_SVD_TRACE") != nullptr;
-        auto t0 = std::chrono::steady_clock::now();
-        if (trace) check(hipStreamSynchronize(s));
-        if (rk) {
-          // Q_L R_L = L^T, Q_R R_R = R^T;  M = Q_L (R_L R_R^T) Q_R^T;  core = U' S V'^T
-          const long rr = rk * rk, rn = rk * nb, nn = nb * nb;
-          check(qr_f64(s, (int)nb, (int)rk, 2 * g, Xq.f64(), Rq.f64(), Qq.f64(), qwork));
-          check(gemm_f64(s, false, true, (int)rk, (int)rk, (int)rk, 1.0, Rq.f64(), rk, rr, Rq.f64() + g * rr, rk, rr,
-                         0.0, Cq.f64(), rk, rr, g));
-          check(svd_f64(s, (int)rk, g, Cq.f64(), Uq.f64(), Sq.f64(), Vq.f64(), cwork, svd_max_sweeps, svd_tol,
-                        host_flags, &sweeps, nullptr));
-          // U = Q_L U', V = Q_R V' in the first r0 columns; the rest (and S beyond r0) are zero
-          check(fill_f64(s, Ub.f64(), 0.0, g * nn));
-          check(fill_f64(s, Vb.f64(), 0.0, g * nn));
-          check(fill_f64(s, Sb.f64(), 0.0, g * nb));
-          check(gemm_f64(s, true, false, (int)nb, (int)rk, (int)rk, 1.0, Qq.f64(), nb, rn, Uq.f64(), rk, rr, 0.0,
-                         Ub.f64(), nb, nn, g));
-          check(gemm_f64(s, true, false, (int)nb, (int)rk, (int)rk, 1.0, Qq.f64() + g * rn, nb, rn, Vq.f64(), rk, rr,
-                         0.0, Vb.f64(), nb, nn, g));
-          check(hipMemcpy2DAsync(Sb.p, sizeof(double) * nb, Sq.p, sizeof(double) * rk, sizeof(double) * rk, g,
-                                 hipMemcpyDeviceToDevice, s));
-        } else {
-          check(svd_f64(s, (int)nb, g, Mb.f64(), Ub.f64(), Sb.f64(), Vb.f64(), work, svd_max_sweeps, svd_tol,
-                        host_flags, &sweeps, warm_all ? V0.f64() : nullptr));
-        }
-        svd_sweeps_total += sweeps;
-        svd_calls += 1;
-        if (trace && ok()) {
-          std::vector<double> sv(nb);
-          check(hipMemcpyAsync(sv.data(), Sb.f64(), sizeof(double) * nb, hipMemcpyDeviceToHost, s));
-          check(hipStreamSynchronize(s));
-          const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-          int r = 0;
-          for (long k = 0; k < nb; ++k) r += sv[k] > 1e-14 * sv[0];
-          const int kc = std::min<long>(reqs[grp[0]].chi, nb) - 1;
-          fprintf(stderr, "[svd] n=%ld r0=%ld batch=%d warm=%d sweeps=%d %.1f ms rank=%d s_chi/s1=%.2e s_2chi/s1=%.2e\n",
-                  nb, rk, g, (int)warm_all, sweeps, ms, r, sv[kc] / sv[0],
-                  sv[std::min<long>(2 * kc + 1, nb - 1)] / sv[0]);
-        }
-      }
-      if (!replayed && svdc_mode == 1 && svdc_slot >= 0) {   // record
-        SvdCacheSlot& sl = svdc_slots[svdc_slot];
-        const long un = (long)g * nb * nb, sn = (long)g * nb;
-        const long need = ((2 * un + sn + 31) / 32) * 32;
-        if (sl.valid && sl.used + need <= sl.cap) {
-          if (!dry && ok()) {
-            double* dst = svdc_buf.f64() + (long)svdc_slot * svdc_per_slot + sl.used;
-            check(hipMemcpyAsync(dst, Ub.p, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
-            check(hipMemcpyAsync(dst + un, Sb.p, sizeof(double) * sn, hipMemcpyDeviceToDevice, s));
-            check(hipMemcpyAsync(dst + un + sn, Vb.p, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
-          }
-          sl.off.push_back(sl.used);
-          sl.nb.push_back(nb);
-          sl.g.push_back(g);
-          sl.used += need;
-        } else {
-          sl.valid = false;   // a later replay of this move recomputes everything
-        }
-      }
-      ar.release(mk);
+      continue;
     }
-    for (int j = 0; j < g && rk == 0; ++j) {
-      int sl = reqs[grp[j]].slot;
-      if (sl >= 0 && sl < (int)warm.size() && warm[sl].n() == nb * nb) {
-        if (!dry && ok())
-          check(hipMemcpyAsync(warm[sl].p, Vb.f64() + (long)j * nb * nb, sizeof(double) * nb * nb,
-                               hipMemcpyDeviceToDevice, s));
-        warm_valid[sl] = 1;
+    // M = L^T R with L, R: r0 x n_b  (entries 0..g-1: L, g..2g-1: R)
+    G.Xq = alloc(F64, {2 * g, rk, nb});
+    G.Rq = alloc(F64, {2 * g, rk, rk});
+    G.Qq = alloc(F64, {2 * g, rk, nb});
+    for (long j = 0; j < g; ++j) {
+      const ProjReq& q = reqs[G.idx[j]];
+      const ProjSaved& P = ps[G.idx[j]];
+      const long na = P.na, offL = j * rk * nb, offR = (g + j) * rk * nb;
+      if (q.fX.p && q.fZ.p && q.rows && rk == q.fZ.n() / nb) {   // L = fX^T rho_B, R = fZ
+        size_t m2 = ar.mark();
+        Ten fX = alloc(F64, {na, rk});
+        if (!dry && ok()) {
+          if (q.fX.dt == F64) {
+            check(hipMemcpyAsync(fX.p, q.fX.p, q.fX.bytes(), hipMemcpyDeviceToDevice, s));
+            check(hipMemcpyAsync(G.Xq.f64() + offR, q.fZ.p, q.fZ.bytes(), hipMemcpyDeviceToDevice, s));
+          } else {
+            check(cast_f32_to_f64(s, q.fX.f32(), fX.f64(), q.fX.n()));
+            check(cast_f32_to_f64(s, q.fZ.f32(), G.Xq.f64() + offR, q.fZ.n()));
+          }
+        }
+        gemm(true, false, (int)rk, (int)nb, (int)na, 1.0, fX, 0, rk, P.rB, 0, nb, 0.0, G.Xq, offL, nb);
+        ar.release(m2);
+      } else if (P.rows) {   // L = rho_B, R = rho_T  (n_a x n_b)
+        if (!dry && ok()) {
+          check(hipMemcpyAsync(G.Xq.f64() + offL, P.rB.p, P.rB.bytes(), hipMemcpyDeviceToDevice, s));
+          check(hipMemcpyAsync(G.Xq.f64() + offR, P.rT.p, P.rT.bytes(), hipMemcpyDeviceToDevice, s));
+        }
+      } else {               // rho stored n_b x n_a: L = rho_B^T, R = rho_T^T
+        permute_into(P.rB, "ab->ba", view_of(*this, G.Xq, offL, {rk, nb}), false);
+        permute_into(P.rT, "ab->ba", view_of(*this, G.Xq, offR, {rk, nb}), false);
       }
     }
-    for (int j = 0; j < g; ++j) {
-      const size_t i = grp[j];
+    // Q_L R_L = L^T, Q_R R_R = R^T;  M = Q_L (R_L R_R^T) Q_R^T;  the core goes into the Jacobi batch
+    void* qwork = ar.alloc(qr_work_bytes((int)nb, (int)rk, 2 * (int)g));
+    if (!dry && ok()) {
+      const long rr = rk * rk;
+      check(qr_f64(s, (int)nb, (int)rk, 2 * (int)g, G.Xq.f64(), G.Rq.f64(), G.Qq.f64(), qwork));
+      check(gemm_f64(s, false, true, (int)rk, (int)rk, (int)rk, 1.0, G.Rq.f64(), rk, rr, G.Rq.f64() + g * rr, rk, rr,
+                     0.0, jM[rk].f64() + G.job0 * rr, rk, rr, (int)g));
+    }
+  }
+  for (long n : sizes) {
+    void* work = ar.alloc(svd_precond_work_bytes((int)n, (int)jobs[n]));
+    if (dry || !ok()) continue;
+    int sweeps = 0;
+    static const bool trace = getenv("SPLITCTM_SVD_TRACE") != nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    if (trace) check(hipStreamSynchronize(s));
+    check(svd_precond_f64(s, (int)n, (int)jobs[n], jM[n].f64(), jU[n].f64(), jS[n].f64(), jV[n].f64(), work,
+                          svd_max_sweeps, svd_tol, host_flags, &sweeps));
+    svd_sweeps_total += sweeps;
+    svd_calls += 1;
+    if (trace && ok()) {
+      check(hipStreamSynchronize(s));
+      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      fprintf(stderr, "[svd] n=%ld batch=%ld sweeps=%d %.1f ms\n", n, jobs[n], sweeps, ms);
+    }
+  }
+  // low-rank route: U = Q_L U', V = Q_R V' in the first r0 columns; the rest (and S beyond r0) are zero
+  for (Group& G : groups) {
+    if (G.replayed || !G.rk || dry || !ok()) continue;
+    const long nb = G.nb, rk = G.rk, g = (long)G.idx.size();
+    const long rr = rk * rk, rn = rk * nb, nn = nb * nb;
+    check(fill_f64(s, G.Ub.f64(), 0.0, g * nn));
+    check(fill_f64(s, G.Vb.f64(), 0.0, g * nn));
+    check(fill_f64(s, G.Sb.f64(), 0.0, g * nb));
+    check(gemm_f64(s, true, false, (int)nb, (int)rk, (int)rk, 1.0, G.Qq.f64(), nb, rn,
+                   jU[rk].f64() + G.job0 * rr, rk, rr, 0.0, G.Ub.f64(), nb, nn, (int)g));
+    check(gemm_f64(s, true, false, (int)nb, (int)rk, (int)rk, 1.0, G.Qq.f64() + g * rn, nb, rn,
+                   jV[rk].f64() + G.job0 * rr, rk, rr, 0.0, G.Vb.f64(), nb, nn, (int)g));
+    check(hipMemcpy2DAsync(G.Sb.p, sizeof(double) * nb, jS[rk].f64() + G.job0 * rk, sizeof(double) * rk,
+                           sizeof(double) * rk, g, hipMemcpyDeviceToDevice, s));
+  }
+  ar.release(mk);
+  // record the decompositions of this call for a later replay
+  for (Group& G : groups) {
+    if (G.replayed || svdc_mode != 1 || svdc_slot < 0) continue;
+    const long nb = G.nb, g = (long)G.idx.size();
+    SvdCacheSlot& sl = svdc_slots[svdc_slot];
+    const long un = g * nb * nb, sn = g * nb;
+    const long need = ((2 * un + sn + 31) / 32) * 32;
+    if (sl.valid && sl.used + need <= sl.cap) {
+      if (!dry && ok()) {
+        double* dst = svdc_buf.f64() + (long)svdc_slot * svdc_per_slot + sl.used;
+        check(hipMemcpyAsync(dst, G.Ub.p, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
+        check(hipMemcpyAsync(dst + un, G.Sb.p, sizeof(double) * sn, hipMemcpyDeviceToDevice, s));
+        check(hipMemcpyAsync(dst + un + sn, G.Vb.p, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
+      }
+      sl.off.push_back(sl.used);
+      sl.nb.push_back(nb);
+      sl.g.push_back(g);
+      sl.used += need;
+    } else {
+      sl.valid = false;   // a later replay of this move recomputes everything
+    }
+  }
+  // projector formation
+  for (Group& G : groups) {
+    const long nb = G.nb;
+    for (size_t j = 0; j < G.idx.size(); ++j) {
+      const size_t i = G.idx[j];
       const ProjReq& q = reqs[i];
       ProjSaved& P = ps[i];
       const long na = P.na;
       const int chi = q.chi;
-      P.U = view_of(*this, Ub, (long)j * nb * nb, {nb, nb});
-      P.S = view_of(*this, Sb, (long)j * nb, {nb});
-      P.V = view_of(*this, Vb, (long)j * nb * nb, {nb, nb});
+      P.U = view_of(*this, G.Ub, (long)j * nb * nb, {nb, nb});
+      P.S = view_of(*this, G.Sb, (long)j * nb, {nb});
+      P.V = view_of(*this, G.Vb, (long)j * nb * nb, {nb, nb});
       P.kr = alloc(F64, {2});   // two ints (k, r) in its first 8 bytes
       P.X = alloc(F64, {nb, chi});
       P.Y = alloc(F64, {nb, chi});

@@ -74,7 +74,6 @@ struct ProjReq {
   int n_a;
   bool rows;
   int chi;
-  int slot;                          // warm-start slot (-1: cold start)
   std::vector<double>* spectrum_out;
   // optional factorisation rho_T = fX^T fZ through a bond of dimension r0
   // (fX: a-legs x r0, fZ: r0 x b-legs; rows layout only): M = (fX^T rho_B)^T fZ
@@ -152,9 +151,6 @@ struct Engine {
   std::vector<Ten> projectors(const Ten& rT, const Ten& rB, int n_a, bool rows, int chi,
                               std::vector<double>* spectrum_out = nullptr);
   std::vector<std::vector<Ten>> projectors_batch(const std::vector<ProjReq>& reqs);
-  // warm-start right singular vectors per projector slot (persistent buffers)
-  std::vector<Ten> warm;
-  std::vector<char> warm_valid;
   long svd_calls = 0;
   bool lowrank_svd = true;           // decompose rank-limited M through its r0 x r0 core
   // Record / replay of projector SVDs per move of a checkpoint block: the

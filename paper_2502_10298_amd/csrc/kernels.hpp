@@ -73,6 +73,11 @@ hipError_t normalize_adjoint_f32(hipStream_t s, const float* y, const float* yba
 // Columns of U whose singular value is zero are left zero.
 // work must hold svd_work_bytes(n, batch) bytes.
 size_t svd_work_bytes(int n, int batch);
+// The same decomposition with QR preconditioning (columns sorted by norm,
+// A P = Q R, Jacobi SVD of R^T); falls back to svd_f64 for n > 4096.
+size_t svd_precond_work_bytes(int n, int batch);
+hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, double* U, double* S, double* V,
+                           void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out);
 // Householder QR of batch tall matrices X (m x k, m >= k, m <= 4096) given as
 // Xt = X^T (k x m row-major, overwritten).  R: k x k upper triangular
 // (row-major), Qt = Q^T (k x m); either may be null.

@@ -551,4 +551,151 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Preconditioned SVD (Drmac and Veselic's QR preconditioning of one-sided
+// Jacobi): with the columns of A sorted by decreasing norm (permutation P),
+// A P = Q R by Householder QR, and the Jacobi SVD of R^T = U_J S V_J^T gives
+//   A = (Q V_J) S (P U_J)^T.
+// R^T has nearly orthogonal columns for graded A, so the Jacobi needs about
+// half the sweeps; the QR costs less than one sweep.
+
+// column norms of row-major n x n matrices (thread = column, coalesced rows)
+__global__ void pre_colnorm_kernel(const double* A_all, int n, double* nrm_all) {
+  const int b = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double* A = A_all + (long)b * n * n;
+  double acc = 0.0;
+  for (int r = 0; r < n; ++r) acc += A[(long)r * n + c] * A[(long)r * n + c];
+  nrm_all[(long)b * n + c] = acc;
+}
+
+// position of column c in the decreasing-norm order (ties: lower index first)
+__global__ void pre_rank_kernel(const double* nrm_all, int n, int* rank_all) {
+  const int b = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double* s = nrm_all + (long)b * n;
+  const double sc = s[c];
+  int r = 0;
+  for (int i = 0; i < n; ++i) r += (s[i] > sc || (s[i] == sc && i < c)) ? 1 : 0;
+  rank_all[(long)b * n + c] = r;
+}
+
+// Xt[rank[c]][r] = A[r][c]  (rows of Xt = the sorted columns of A), 32 x 32
+// tiles through LDS so that reads and writes are both coalesced
+__global__ void pre_gather_kernel(const double* A_all, const int* rank_all, int n, double* Xt_all) {
+  const int b = blockIdx.z;
+  const double* A = A_all + (long)b * n * n;
+  double* Xt = Xt_all + (long)b * n * n;
+  const int* rk = rank_all + (long)b * n;
+  __shared__ double tile[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 8 rows per pass
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    tile[k][tx] = (r < n && c < n) ? A[(long)r * n + c] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (c < n && r < n) Xt[(long)rk[c] * n + r] = tile[tx][k];
+  }
+}
+
+// V[c][:] = UJ[rank[c]][:]
+__global__ void pre_unpermute_rows_kernel(const double* UJ_all, const int* rank_all, int n, double* V_all) {
+  const int c = blockIdx.x, b = blockIdx.y;
+  const double* src = UJ_all + (long)b * n * n + (long)rank_all[(long)b * n + c] * n;
+  double* dst = V_all + (long)b * n * n + (long)c * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// B = A^T for row-major n x n matrices (32 x 32 LDS tiles)
+__global__ void pre_transpose_kernel(const double* A_all, int n, double* B_all) {
+  const int b = blockIdx.z;
+  const double* A = A_all + (long)b * n * n;
+  double* B = B_all + (long)b * n * n;
+  __shared__ double tile[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    tile[k][tx] = (r < n && c < n) ? A[(long)r * n + c] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (c < n && r < n) B[(long)c * n + r] = tile[tx][k];
+  }
+}
+
+struct PreLayout {
+  size_t offX, offR, offQ, offUJ, offVJ, offN, offRk, offQW, offJW, total;
+};
+
+static PreLayout pre_layout(int n, int batch) {
+  PreLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t nn = sizeof(double) * (size_t)n * n * batch;
+  L.offX = take(nn);
+  L.offR = take(nn);
+  L.offQ = take(nn);
+  L.offUJ = take(nn);
+  L.offVJ = take(nn);
+  L.offN = take(sizeof(double) * (size_t)n * batch);
+  L.offRk = take(sizeof(int) * (size_t)n * batch);
+  L.offQW = take(qr_work_bytes(n, n, batch));
+  L.offJW = take(svd_work_bytes(n, batch));
+  L.total = off;
+  return L;
+}
+
+size_t svd_precond_work_bytes(int n, int batch) {
+  return n <= 4096 ? pre_layout(n, batch).total : svd_work_bytes(n, batch);
+}
+
+hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, double* U, double* S, double* V,
+                           void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out) {
+  if (n > 4096)   // the QR holds the rows of a panel in registers
+    return svd_f64(s, n, batch, A, U, S, V, work, max_sweeps, tol, host_flags, sweeps_out, nullptr);
+  PreLayout L = pre_layout(n, batch);
+  char* w = (char*)work;
+  double* Xt = (double*)(w + L.offX);
+  double* R = (double*)(w + L.offR);
+  double* Qt = (double*)(w + L.offQ);
+  double* UJ = (double*)(w + L.offUJ);
+  double* VJ = (double*)(w + L.offVJ);
+  double* nrm = (double*)(w + L.offN);
+  int* rk = (int*)(w + L.offRk);
+  const long nn = (long)n * n;
+  hipLaunchKernelGGL(pre_colnorm_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, A, n, nrm);
+  hipLaunchKernelGGL(pre_rank_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, (const double*)nrm, n, rk);
+  hipLaunchKernelGGL(pre_gather_kernel, dim3((n + 31) / 32, (n + 31) / 32, batch), dim3(256), 0, s, A,
+                     (const int*)rk, n, Xt);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = qr_f64(s, n, n, batch, Xt, R, Qt, w + L.offQW);
+  // the Jacobi input is R^T: its columns (rows of R) are the rows of Gt, i.e. M = R^T
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(pre_transpose_kernel, dim3((n + 31) / 32, (n + 31) / 32, batch), dim3(256), 0, s,
+                       (const double*)R, n, Xt);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = svd_f64(s, n, batch, Xt, UJ, S, VJ, w + L.offJW, max_sweeps, tol, host_flags, sweeps_out, nullptr);
+  // U = Q V_J,  V = P U_J
+  if (e == hipSuccess) e = gemm_f64(s, true, false, n, n, n, 1.0, Qt, n, nn, VJ, n, nn, 0.0, U, n, nn, batch);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(pre_unpermute_rows_kernel, dim3(n, batch), dim3(256), 0, s, (const double*)UJ,
+                       (const int*)rk, n, V);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
 }  // namespace sctm
