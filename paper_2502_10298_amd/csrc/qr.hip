@@ -4,16 +4,16 @@
 //
 // Blocked right-looking Householder with panels of 16, 8 or 4 columns (as
 // many as the rows held per thread allow without register spills):
-//   panel:    one workgroup of 1024 threads per matrix factors the panel in
-//             registers (thread t holds rows p0 + t + 1024 r), one reflector
+//   panel:    one workgroup per matrix factors the panel in registers
+//             (thread t holds rows p0 + t + NT r), one reflector
 //             per column (LAPACK's dlarfg convention: beta = -sign(x0) |x|,
 //             tau = (beta - x0) / beta, v = x / (x0 - beta) with v_0 = 1) and
 //             builds the triangular factor T of the block reflector
 //             H_1 ... H_PW = I - V T V^T (forward, columnwise);
 //   trailing: X_trail <- H^T X_trail, i.e. Xt_trail <- Xt_trail - (Xt_trail V) T V^T,
-//             three batched GEMMs on the matrix cores;
+//             one fused kernel on the matrix cores;
 //   Q:        Q = H_1 ... H_p [I; 0], accumulated backwards over the panels,
-//             Qt <- Qt - (Qt V) T^T V^T on the trailing block, again GEMMs.
+//             Qt <- Qt - (Qt V) T^T V^T on the trailing block, the same kernel.
 // Householder QR is backward stable: Q is orthonormal to working accuracy
 // and X = Q R + dX with |dX| ~ eps |X|, whatever the rank of X.
 #include "kernels.hpp"
@@ -29,7 +29,7 @@ static constexpr int TSLOT = 4;   // narrowest panel: one T block per TSLOT colu
 
 struct QrLayout {
   long sX, sT;
-  size_t offV, offT, offW1, offW2, total;
+  size_t offV, offT, total;
 };
 
 static QrLayout qr_layout(int m, int k, int batch) {
@@ -45,18 +45,16 @@ static QrLayout qr_layout(int m, int k, int batch) {
   };
   L.offV = take(sizeof(double) * L.sX * batch);                // reflectors as rows [k][m]
   L.offT = take(sizeof(double) * L.sT * batch);                // T of every panel
-  L.offW1 = take(sizeof(double) * (size_t)k * PW * batch);     // (rows x PW) products
-  L.offW2 = take(sizeof(double) * (size_t)k * PW * batch);
   L.total = off;
   return L;
 }
 
 size_t qr_work_bytes(int m, int k, int batch) { return qr_layout(m, k, batch).total; }
 
-// Block-wide sum of NV values per thread (1024 threads = 16 wavefronts);
-// red: LDS scratch of 16 * NV doubles; the sums land in out[0 .. NV-1] (LDS)
-// for every thread to read.
-template <int NV>
+// Block-wide sum of NV values per thread over NW wavefronts; red: LDS
+// scratch of NW * NV doubles; the sums land in out[0 .. NV-1] (LDS) for every
+// thread to read.
+template <int NW, int NV>
 __device__ inline void block_sum(double (&v)[NV], double* red, double* out) {
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -71,7 +69,7 @@ __device__ inline void block_sum(double (&v)[NV], double* red, double* out) {
   __syncthreads();
   if (threadIdx.x < NV) {
     double a = 0.0;
-    for (int w = 0; w < 16; ++w) a += red[w * NV + threadIdx.x];
+    for (int w = 0; w < NW; ++w) a += red[w * NV + threadIdx.x];
     out[threadIdx.x] = a;
   }
   __syncthreads();
@@ -80,9 +78,10 @@ __device__ inline void block_sum(double (&v)[NV], double* red, double* out) {
 // Factor the panel of columns p0 .. p0 + w - 1 (rows p0 .. m - 1) of every
 // matrix; writes the reflectors (below the diagonal) and R (on and above it)
 // back into Xt, the reflectors as full rows into Vr (zeros above, 1 on the
-// diagonal) and the panel's T.  RM = rows per thread (m - p0 <= 1024 RM).
-template <int RM, int PWT>
-__global__ __launch_bounds__(1024) void qr_panel_kernel(double* Xt_all, double* Vr_all, double* T_all, int m, int k,
+// diagonal) and the panel's T.  NT threads, RM rows per thread
+// (m - p0 <= NT RM), PWT columns.
+template <int NT, int RM, int PWT>
+__global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr_all, double* T_all, int m, int k,
                                                         long sX, long sT, int p0) {
   const int b = blockIdx.x;
   double* Xt = Xt_all + b * sX;
@@ -90,14 +89,15 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* Xt_all, double* 
   double* Tp = T_all + b * sT + (long)(p0 / TSLOT) * PW * PW;
   const int w = min(PWT, k - p0);
   const int t = threadIdx.x;
-  __shared__ double red[16 * PW];
+  constexpr int NW = NT / 64;   // wavefronts
+  __shared__ double red[NW * PW];
   __shared__ double dots[PW];
   __shared__ double x0s;
   __shared__ double Ts[PW][PW];
   double x[RM][PWT];
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
-    const int i = p0 + t + 1024 * r;
+    const int i = p0 + t + NT * r;
 #pragma unroll
     for (int l = 0; l < PWT; ++l) x[r][l] = (i < m && l < w) ? Xt[(long)(p0 + l) * m + i] : 0.0;
   }
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* Xt_all, double* 
     double ss[1] = {0.0};
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
-      const int i = p0 + t + 1024 * r;
+      const int i = p0 + t + NT * r;
 #pragma unroll
       for (int l = 0; l < PWT; ++l)
         if (l == j) {
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* Xt_all, double* 
           if (i == c) x0s = x[r][l];
         }
     }
-    block_sum<1>(ss, red, dots);
+    block_sum<NW, 1>(ss, red, dots);
     const double sq = dots[0], x0 = x0s;
     double tau = 0.0, beta = x0, scale = 0.0;
     if (sq > 0.0) {
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* Xt_all, double* 
     double vi[RM];
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
-      const int i = p0 + t + 1024 * r;
+      const int i = p0 + t + NT * r;
 #pragma unroll
       for (int l = 0; l < PWT; ++l)
         if (l == j) {
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* Xt_all, double* 
         double a = 0.0;
 #pragma unroll
         for (int r = 0; r < RM; ++r) {
-          const int i = p0 + t + 1024 * r;
+          const int i = p0 + t + NT * r;
           // column l < j holds v_l below its diagonal p0 + l (< c): rows >= c carry v_l values
           a += vi[r] * ((l < j) ? ((i == p0 + l) ? 1.0 : x[r][l]) : x[r][l]);
         }
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* Xt_all, double* 
       __syncthreads();
       if (t < PWT) {
         double a = 0.0;
-        for (int q = 0; q < 16; ++q) a += red[q * PWT + t];
+        for (int q = 0; q < NW; ++q) a += red[q * PWT + t];
         dots[t] = a;
       }
       __syncthreads();
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* Xt_all, double* 
   // write back: Xt rows p0 .. p0 + w - 1, the reflector rows, T
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
-    const int i = p0 + t + 1024 * r;
+    const int i = p0 + t + NT * r;
     if (i < m)
 #pragma unroll
       for (int l = 0; l < PWT; ++l)
@@ -193,8 +193,88 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* Xt_all, double* 
   }
   // rows of Vr before p0 are zero (the reflectors act on rows >= p0 + l)
   for (int l = 0; l < w; ++l)
-    for (int i = t; i < p0; i += 1024) Vr[(long)(p0 + l) * m + i] = 0.0;
+    for (int i = t; i < p0; i += NT) Vr[(long)(p0 + l) * m + i] = 0.0;
   if (t < PW * PW) Tp[t] = Ts[t / PW][t % PW];
+}
+
+// Y <- Y - ((Y V) T') V^T for the rows of Y (nt rows of length len, leading
+// dimension ld), V^T = the panel's reflectors (pw <= 16 rows of length len,
+// leading dimension ld) and T' = T (trailing update of the factorisation) or
+// T^T (accumulation of Q).  One workgroup per 16 rows of Y: the four
+// wavefronts split the length for Y V (MFMA, partial products summed in LDS
+// in a fixed order), form (Y V) T' in LDS, then split the column tiles of
+// the rank-pw update (MFMA again).  v_mfma_f64_16x16x4: A lane l holds
+// A[l%16][l/16], B lane l holds B[l/16][l%16], D lane l register r holds
+// D[4r + l/16][l%16]; in Y V lane l takes the summation index
+// k = kb + 16 (l/16) + j at step j, so that each lane streams 16 consecutive
+// entries of its row of Y and of V.
+template <bool TRANS_T>
+__global__ __launch_bounds__(256) void qr_update_kernel(double* Y_all, long sY, int nt, int len, int ld,
+                                                        const double* V_all, long sV, const double* T_all, long sT,
+                                                        int pw) {
+  typedef double d4u __attribute__((ext_vector_type(4)));
+  const int b = blockIdx.y;
+  double* Y = Y_all + b * sY;
+  const double* V = V_all + b * sV;
+  const double* T = T_all + b * sT;
+  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
+  const int row0 = blockIdx.x * 16;
+  __shared__ double Ts[PW][PW + 1];
+  __shared__ double red[4][16][17];
+  __shared__ double w2[16][PW + 1];
+  for (int e = tid; e < PW * PW; e += 256) Ts[e / PW][e % PW] = T[e];
+  // partial W1 = Y V over the wave's quarter of the length (64-entry blocks)
+  const int nblk = (len + 63) / 64;
+  const int ra = row0 + (l & 15);
+  const bool rok = ra < nt, vok = (l & 15) < pw;
+  const double* yrow = Y + (long)ra * ld;
+  const double* vrow = V + (long)(l & 15) * ld;
+  d4u d = {0, 0, 0, 0};
+  for (int blk = wv; blk < nblk; blk += 4) {
+    const int k0 = blk * 64 + 16 * (l >> 4);
+    double av[16], bv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int kk = k0 + j;
+      av[j] = (rok && kk < len) ? yrow[kk] : 0.0;
+      bv[j] = (vok && kk < len) ? vrow[kk] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], d, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wv][4 * r + (l >> 4)][l & 15] = d[r];
+  __syncthreads();
+  // W2 = W1 T'  (16 x pw), W1 = sum of the four partials
+  {
+    const int i = tid >> 4, c = tid & 15;
+    double a = 0.0;
+    for (int j = 0; j < pw; ++j) {
+      const double w1 = (red[0][i][j] + red[1][i][j]) + (red[2][i][j] + red[3][i][j]);
+      a += w1 * (TRANS_T ? Ts[c][j] : Ts[j][c]);
+    }
+    w2[i][c] = (c < pw) ? a : 0.0;
+  }
+  __syncthreads();
+  // Y -= W2 V^T, the waves taking 16-column tiles in turn
+  const int nk = (pw + 3) / 4;
+  for (int i0 = wv * 16; i0 < len; i0 += 64) {
+    const int ci = i0 + (l & 15);
+    d4u u = {0, 0, 0, 0};
+    for (int kk = 0; kk < nk; ++kk) {
+      const int j = kk * 4 + (l >> 4);
+      const double a = (j < pw) ? w2[l & 15][j] : 0.0;
+      const double bb = (j < pw && ci < len) ? V[(long)j * ld + ci] : 0.0;
+      u = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, u, 0, 0, 0);
+    }
+    if (ci < len) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = row0 + 4 * r + (l >> 4);
+        if (rr < nt) Y[(long)rr * ld + ci] -= u[r];
+      }
+    }
+  }
 }
 
 // R (k x k, row-major, zero below the diagonal) from the factored Xt
@@ -227,47 +307,57 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
   char* w = (char*)work;
   double* Vr = (double*)(w + L.offV);
   double* T = (double*)(w + L.offT);
-  double* W1 = (double*)(w + L.offW1);
-  double* W2 = (double*)(w + L.offW2);
   hipError_t e = hipSuccess;
-  // panels: as wide as the rows per thread allow without register spills
+  // panels: 256 threads with up to 4 rows each and 16 columns, or 8 rows
+  // and 8 columns; beyond 2048 rows 1024 threads with 4 columns
   struct Panel {
-    int p0, pw, rm;
+    int p0, pw, nt_threads, rm;
   };
   std::vector<Panel> pans;
   for (int p0 = 0; p0 < k;) {
-    const int rm = (m - p0 + 1023) / 1024;
-    const int pw = std::min(rm <= 1 ? 16 : (rm == 2 ? 8 : 4), k - p0);
-    pans.push_back({p0, pw, rm});
-    p0 += pw;
+    const int rows = m - p0;
+    Panel P;
+    P.p0 = p0;
+    if (rows <= 2048) {
+      const int need = (rows + 255) / 256;
+      P.nt_threads = 256;
+      P.rm = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+      P.pw = std::min(P.rm == 8 ? 8 : 16, k - p0);
+    } else {
+      P.nt_threads = 1024;
+      P.rm = (rows + 1023) / 1024;
+      P.pw = std::min(4, k - p0);
+    }
+    pans.push_back(P);
+    p0 += P.pw;
   }
   for (const Panel& P : pans) {
     if (e != hipSuccess) break;
     const int p0 = P.p0, pw = P.pw, rows = m - p0;
-    dim3 g(batch), blk(1024);
-    if (P.rm <= 1)
-      hipLaunchKernelGGL((qr_panel_kernel<1, 16>), g, blk, 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
-    else if (P.rm == 2)
-      hipLaunchKernelGGL((qr_panel_kernel<2, 8>), g, blk, 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
-    else if (P.rm == 3)
-      hipLaunchKernelGGL((qr_panel_kernel<3, 4>), g, blk, 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
-    else
-      hipLaunchKernelGGL((qr_panel_kernel<4, 4>), g, blk, 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
+    const dim3 g(batch);
+    if (P.nt_threads == 256) {
+      if (P.rm == 1)
+        hipLaunchKernelGGL((qr_panel_kernel<256, 1, 16>), g, dim3(256), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
+      else if (P.rm == 2)
+        hipLaunchKernelGGL((qr_panel_kernel<256, 2, 16>), g, dim3(256), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
+      else if (P.rm == 4)
+        hipLaunchKernelGGL((qr_panel_kernel<256, 4, 16>), g, dim3(256), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
+      else
+        hipLaunchKernelGGL((qr_panel_kernel<256, 8, 8>), g, dim3(256), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
+    } else {
+      if (P.rm <= 3)
+        hipLaunchKernelGGL((qr_panel_kernel<1024, 3, 4>), g, dim3(1024), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
+      else
+        hipLaunchKernelGGL((qr_panel_kernel<1024, 4, 4>), g, dim3(1024), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
+    }
     e = hipGetLastError();
     const int nt = k - p0 - pw;   // trailing columns of X = rows of Xt
     if (nt <= 0 || e != hipSuccess) continue;
-    double* Xtr = Xt + (long)(p0 + pw) * m + p0;     // Xt_trail: nt x rows, ld m
-    const double* V = Vr + (long)p0 * m + p0;        // V^T: pw x rows, ld m
-    const double* Tp = T + (long)(p0 / TSLOT) * PW * PW;
-    // W1 = Xt_trail V  (nt x pw)
-    e = gemm_f64(s, false, true, nt, pw, rows, 1.0, Xtr, m, L.sX, V, m, L.sX, 0.0, W1, pw, (long)k * PW, batch);
-    // W2 = W1 T
-    if (e == hipSuccess)
-      e = gemm_f64(s, false, false, nt, pw, pw, 1.0, W1, pw, (long)k * PW, Tp, PW, L.sT, 0.0, W2, pw, (long)k * PW,
-                   batch);
-    // Xt_trail -= W2 V^T
-    if (e == hipSuccess)
-      e = gemm_f64(s, false, false, nt, rows, pw, -1.0, W2, pw, (long)k * PW, V, m, L.sX, 1.0, Xtr, m, L.sX, batch);
+    // Xt_trail (nt x rows, ld m) -= ((Xt_trail V) T) V^T
+    hipLaunchKernelGGL(qr_update_kernel<false>, dim3((nt + 15) / 16, batch), dim3(256), 0, s,
+                       Xt + (long)(p0 + pw) * m + p0, L.sX, nt, rows, m, (const double*)(Vr + (long)p0 * m + p0),
+                       L.sX, (const double*)(T + (long)(p0 / TSLOT) * PW * PW), L.sT, pw);
+    e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
   if (R) {
@@ -280,16 +370,11 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
   for (int pi = (int)pans.size() - 1; pi >= 0 && e == hipSuccess; --pi) {
     const int p0 = pans[pi].p0, pw = pans[pi].pw;
     const int rows = m - p0, nt = k - p0;
-    double* Qs = Qt + (long)p0 * m + p0;             // Qt rows p0.., columns p0..
-    const double* V = Vr + (long)p0 * m + p0;
-    const double* Tp = T + (long)(p0 / TSLOT) * PW * PW;
-    // W1 = Qt_sub V (nt x pw);  W2 = W1 T^T;  Qt_sub -= W2 V^T
-    e = gemm_f64(s, false, true, nt, pw, rows, 1.0, Qs, m, L.sX, V, m, L.sX, 0.0, W1, pw, (long)k * PW, batch);
-    if (e == hipSuccess)
-      e = gemm_f64(s, false, true, nt, pw, pw, 1.0, W1, pw, (long)k * PW, Tp, PW, L.sT, 0.0, W2, pw, (long)k * PW,
-                   batch);
-    if (e == hipSuccess)
-      e = gemm_f64(s, false, false, nt, rows, pw, -1.0, W2, pw, (long)k * PW, V, m, L.sX, 1.0, Qs, m, L.sX, batch);
+    // Qt_sub (rows p0.., columns p0..) -= ((Qt_sub V) T^T) V^T
+    hipLaunchKernelGGL(qr_update_kernel<true>, dim3((nt + 15) / 16, batch), dim3(256), 0, s,
+                       Qt + (long)p0 * m + p0, L.sX, nt, rows, m, (const double*)(Vr + (long)p0 * m + p0), L.sX,
+                       (const double*)(T + (long)(p0 / TSLOT) * PW * PW), L.sT, pw);
+    e = hipGetLastError();
   }
   return e;
 }
