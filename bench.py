@@ -37,6 +37,7 @@ MFMA_PEAKS = {
     "gemm_fp64": (78.6, "fp64 MFMA"),
     "gemm_fp32": (157.3, "fp32 MFMA"),
     "gemm_bf16x3": (2500.0 / 3.0, "bf16 MFMA 2500 / 3 products"),
+    "gemm_bf16x6": (2500.0 / 6.0, "bf16 MFMA 2500 / 6 products"),
     "jacobi_gram": (78.6, "fp64 MFMA"),
     "jacobi_solve": (78.6, "fp64 MFMA"),
     "jacobi_rotate": (78.6, "fp64 MFMA"),

@@ -53,7 +53,12 @@ typedef enum {
   CTM_ENUMERIC = 5
 } ctm_status;
 
-typedef enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16X3 = 2 } ctm_precision;
+/* Contraction precision: FP64; FP32 (FP32 matrix cores); BF16X3 = FP32
+ * operands split as hi + lo in bf16, products lo*hi + hi*lo + hi*hi on the
+ * BF16 matrix cores with FP32 accumulation (error ~2^-16 relative per
+ * product); BF16X6 = three-way split hi + mid + lo with the six products of
+ * total order below 3 (error near FP32 rounding). */
+typedef enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16X3 = 2, CTM_BF16X6 = 3 } ctm_precision;
 
 /* Boundary of ctm_init: IDENTITY = chi_E = 1 corners and transfer tensors
  * that trace the ket and bra virtual legs (independent of A); PRODUCT = every
@@ -125,7 +130,7 @@ ctm_status ctm_last_stats(ctm_ctx* ctx, double* gemm_flops, double* svd_sweeps);
 
 /* Diagnostics: the kernels behind the calls above, exposed for kernel-level
  * checks.  ctm_debug_gemm: C[M][N] = op(A) op(B), row-major, prec CTM_FP64
- * (double) or CTM_FP32 / CTM_BF16X3 (float); transA: A stored K x M, transB: B
+ * (double) or CTM_FP32 / CTM_BF16X3 / CTM_BF16X6 (float); transA: A stored K x M, transB: B
  * stored N x K.  work: NULL, or device scratch of ctm_debug_gemm_work_bytes
  * bytes; when that size is nonzero (long K, few 64 x 64 output tiles) the
  * product runs split over K, as the contractions of the library do.
@@ -153,7 +158,7 @@ ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S
  * after each call the elapsed times are added up per class.  Enabling (or
  * disabling) resets the totals.  Classes: 0 GEMM FP64, 1 GEMM FP32, 2 GEMM
  * BF16x3, 3 Jacobi Gram matrices, 4 Jacobi 32 x 32 eigensolves, 5 Jacobi
- * rotations of G and V.  *ms = summed kernel time, *launches = number of
+ * rotations of G and V, 6 GEMM BF16x6.  *ms = summed kernel time, *launches = number of
  * launches, *flops and *bytes = algorithmic work and memory traffic of those
  * launches (GEMM: 2 M N K flops and the operands read and written once;
  * Gram: the pairs' columns read once; eigensolve: partial Gram matrices read

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsplitctm.so")
 
 CTM_OK, CTM_EINVAL, CTM_ENOMEM, CTM_EDEVICE, CTM_ENOTCONV, CTM_ENUMERIC = range(6)
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 INIT = {"identity": 0, "product": 1}
 
 EXPORTED = ("ctm_workspace_size", "ctm_init", "ctm_sweep", "ctm_projectors", "ctm_projectors_elems",
@@ -25,7 +25,7 @@ EXPORTED = ("ctm_workspace_size", "ctm_init", "ctm_sweep", "ctm_projectors", "ct
             "ctm_last_stats", "ctm_debug_gemm_work_bytes", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd", "ctm_debug_qr_work_bytes", "ctm_debug_qr",
             "ctm_kernel_timing_enable", "ctm_kernel_timing", "ctm_destroy", "ctm_strerror")
 KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "gemm_bf16x3": 2, "jacobi_gram": 3, "jacobi_solve": 4,
-                  "jacobi_rotate": 5}
+                  "jacobi_rotate": 5, "gemm_bf16x6": 6}
 
 
 class CtmError(RuntimeError):

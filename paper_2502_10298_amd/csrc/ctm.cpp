@@ -555,7 +555,7 @@ ctm_status validate(const ctm_config* cfg) {
   if (!cfg) return CTM_EINVAL;
   if (cfg->Lx < 1 || cfg->Ly < 1 || cfg->Lx > 8 || cfg->Ly > 8) return CTM_EINVAL;
   if (cfg->p < 1 || cfg->D < 1 || cfg->chi_E < 1 || cfg->chi_I < 1) return CTM_EINVAL;
-  if (cfg->contract_prec < CTM_FP64 || cfg->contract_prec > CTM_BF16X3) return CTM_EINVAL;
+  if (cfg->contract_prec < CTM_FP64 || cfg->contract_prec > CTM_BF16X6) return CTM_EINVAL;
   if (cfg->init != CTM_INIT_IDENTITY && cfg->init != CTM_INIT_PRODUCT) return CTM_EINVAL;
   if (cfg->init == CTM_INIT_IDENTITY && cfg->chi_I < cfg->D) return CTM_EINVAL;
   return CTM_OK;
@@ -575,7 +575,7 @@ void setup_ctx(ctm_ctx* c, const ctm_config* cfg, void* ws, size_t bytes, hipStr
   E.ar.dry = dry;
   E.ar.base = (char*)ws;
   E.ar.cap = bytes;
-  E.prec = cfg->contract_prec == CTM_FP64 ? Prec::F64 : (cfg->contract_prec == CTM_FP32 ? Prec::F32 : Prec::BF16X3);
+  E.prec = (Prec)cfg->contract_prec;
   E.cdt = cfg->contract_prec == CTM_FP64 ? F64 : F32;
   E.cutoff = cfg->svd_rel_cutoff > 0 ? cfg->svd_rel_cutoff : 1e-12;
   E.adj_eps = cfg->svd_adj_eps > 0 ? cfg->svd_adj_eps : 1e-12;
@@ -1125,7 +1125,7 @@ size_t ctm_debug_gemm_work_bytes(int prec, int M, int N, int K) {
 
 ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K, const void* A, const void* B,
                           void* C, void* work, void* stream) {
-  if (M < 0 || N < 0 || K < 1 || !A || !B || !C || prec < 0 || prec > 2) return CTM_EINVAL;
+  if (M < 0 || N < 0 || K < 1 || !A || !B || !C || prec < 0 || prec > 3) return CTM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const long lda = transA ? M : K, ldb = transB ? K : N;
   const bool split = work && splitk_scratch_elems(M, N, K) > 0;
@@ -1136,7 +1136,7 @@ ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K,
               : gemm_f64(s, transA, transB, M, N, K, 1.0, (const double*)A, lda, 0, (const double*)B, ldb, 0, 0.0,
                          (double*)C, N, 0, 1);
   else {
-    const Prec md = prec == CTM_FP32 ? Prec::F32 : Prec::BF16X3;
+    const Prec md = (Prec)prec;
     e = split ? gemm_f32_splitk(s, md, transA, transB, M, N, K, 1.f, (const float*)A, lda, (const float*)B, ldb, 0.f,
                                 (float*)C, N, (float*)work)
               : gemm_f32(s, md, transA, transB, M, N, K, 1.f, (const float*)A, lda, 0, (const float*)B, ldb, 0, 0.f,

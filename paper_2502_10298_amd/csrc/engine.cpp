@@ -228,7 +228,7 @@ void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten
         check(gemm_f64_splitk(s, tA, tB, M, N, K, alpha, A.f64() + offA, lda, B.f64() + offB, ldb, beta,
                               C.f64() + offC, ldc, P.f64()));
       else
-        check(gemm_f32_splitk(s, prec == Prec::BF16X3 ? Prec::BF16X3 : Prec::F32, tA, tB, M, N, K, (float)alpha,
+        check(gemm_f32_splitk(s, prec, tA, tB, M, N, K, (float)alpha,
                               A.f32() + offA, lda, B.f32() + offB, ldb, (float)beta, C.f32() + offC, ldc, P.f32()));
     }
     ar.release(mk);
@@ -261,7 +261,7 @@ void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten
     check(gemm_f64(s, tA, tB, M, N, K, alpha, A.f64() + offA, lda, 0, B.f64() + offB, ldb, 0, beta,
                    C.f64() + offC, ldc, 0, 1));
   else
-    check(gemm_f32(s, prec == Prec::BF16X3 ? Prec::BF16X3 : Prec::F32, tA, tB, M, N, K, (float)alpha,
+    check(gemm_f32(s, prec, tA, tB, M, N, K, (float)alpha,
                    A.f32() + offA, lda, 0, B.f32() + offB, ldb, 0, (float)beta, C.f32() + offC, ldc, 0, 1));
   if (timed) {
     check(hipStreamSynchronize(s));

@@ -133,26 +133,34 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
 }
 
 // ---------------------------------------------------------------------------
-// BF16x3: FP32 operands split into bf16 hi + lo in the LDS staging; BK = 32.
+// Split BF16 products: FP32 operands split into NS bf16 terms in the LDS
+// staging (x = hi + lo, or hi + mid + lo), BK = 32, and the cross products
+// of total order below NS on the BF16 matrix cores with FP32 accumulation,
+// smallest first: NS = 2 (BF16x3) lo*hi + hi*lo + hi*hi; NS = 3 (BF16x6)
+// adds mid*mid and the hi*mid, mid*hi, hi*lo, lo*hi terms of the three-way
+// split, which leaves a residual near the FP32 rounding of the operands.
 // ---------------------------------------------------------------------------
-__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;                  // round to nearest even
-  lo = (__bf16)(x - (float)hi);
+template <int NS>
+__device__ inline void split_bf16(float x, __bf16 (&out)[NS]) {
+  float r = x;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    out[q] = (__bf16)r;            // round to nearest even
+    r = r - (float)out[q];
+  }
 }
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(int M, int N, int K, float alpha,
-                                                          const float* __restrict__ A, long lda, long sA,
-                                                          const float* __restrict__ B, long ldb, long sB,
-                                                          float beta, float* __restrict__ C, long ldc,
-                                                          long sC) {
+template <bool TA, bool TB, int NS>
+__global__ __launch_bounds__(256) void gemm_bf16s_kernel(int M, int N, int K, float alpha,
+                                                         const float* __restrict__ A, long lda, long sA,
+                                                         const float* __restrict__ B, long ldb, long sB,
+                                                         float beta, float* __restrict__ C, long ldc, long sC) {
   constexpr int BK = 32;
   // m-major rows of 32 k (bf16) for A, n-major rows of 32 k for B: one lane
-  // fetches 8 consecutive k of one row as a 16-byte vector.
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][BK + 8];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[BM][BK + 8];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][BK + 8];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN][BK + 8];
+  // fetches 8 consecutive k of one row as a 16-byte vector.  Term q of the
+  // split of A lives in As[q], of B in Bs[q].
+  __shared__ __attribute__((aligned(16))) __bf16 As[NS][BM][BK + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][BN][BK + 8];
   const long bz = blockIdx.z;
   A += bz * sA;
   B += bz * sB;
@@ -167,22 +175,25 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(int M, int N, int K, f
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
 
   for (int k0 = 0; k0 < K; k0 += BK) {
+    __bf16 sp[NS];
     // A panel: 64 rows (m) x 32 k = 2048 values, 8 per thread
     if (!TA) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         int r = (tid >> 5) + 8 * i, c = tid & 31;
         int m = bm + r, k = k0 + c;
-        float v = (m < M && k < K) ? A[(long)m * lda + k] : 0.f;
-        split_bf16(v, Ah[r][c], Al[r][c]);
+        split_bf16<NS>((m < M && k < K) ? A[(long)m * lda + k] : 0.f, sp);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) As[q][r][c] = sp[q];
       }
     } else {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         int r = (tid >> 6) + 4 * i, c = tid & 63;   // r = k, c = m
         int k = k0 + r, m = bm + c;
-        float v = (m < M && k < K) ? A[(long)k * lda + m] : 0.f;
-        split_bf16(v, Ah[c][r], Al[c][r]);
+        split_bf16<NS>((m < M && k < K) ? A[(long)k * lda + m] : 0.f, sp);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) As[q][c][r] = sp[q];
       }
     }
     if (!TB) {
@@ -190,35 +201,40 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(int M, int N, int K, f
       for (int i = 0; i < 8; ++i) {
         int r = (tid >> 6) + 4 * i, c = tid & 63;   // r = k, c = n
         int k = k0 + r, n = bn + c;
-        float v = (n < N && k < K) ? B[(long)k * ldb + n] : 0.f;
-        split_bf16(v, Bh[c][r], Bl[c][r]);
+        split_bf16<NS>((n < N && k < K) ? B[(long)k * ldb + n] : 0.f, sp);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) Bs[q][c][r] = sp[q];
       }
     } else {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         int r = (tid >> 5) + 8 * i, c = tid & 31;   // r = n, c = k
         int n = bn + r, k = k0 + c;
-        float v = (n < N && k < K) ? B[(long)n * ldb + k] : 0.f;
-        split_bf16(v, Bh[r][c], Bl[r][c]);
+        split_bf16<NS>((n < N && k < K) ? B[(long)n * ldb + k] : 0.f, sp);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) Bs[q][r][c] = sp[q];
       }
     }
     __syncthreads();
     const int kq = 8 * (lane >> 4);
-    bf8 ah[2], al[2], bh[2], bl[2];
+    bf8 a[NS][2], bb[NS][2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      ah[t] = *reinterpret_cast<const bf8*>(&Ah[wm * 32 + t * 16 + (lane & 15)][kq]);
-      al[t] = *reinterpret_cast<const bf8*>(&Al[wm * 32 + t * 16 + (lane & 15)][kq]);
-      bh[t] = *reinterpret_cast<const bf8*>(&Bh[wn * 32 + t * 16 + (lane & 15)][kq]);
-      bl[t] = *reinterpret_cast<const bf8*>(&Bl[wn * 32 + t * 16 + (lane & 15)][kq]);
-    }
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[q][t] = *reinterpret_cast<const bf8*>(&As[q][wm * 32 + t * 16 + (lane & 15)][kq]);
+        bb[q][t] = *reinterpret_cast<const bf8*>(&Bs[q][wn * 32 + t * 16 + (lane & 15)][kq]);
+      }
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj) {
-        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ti], bh[tj], acc[ti][tj], 0, 0, 0);
-        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bl[tj], acc[ti][tj], 0, 0, 0);
-        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bh[tj], acc[ti][tj], 0, 0, 0);
+        // terms of total order o = qa + qb < NS, highest order (smallest) first
+#pragma unroll
+        for (int o = NS - 1; o >= 0; --o)
+#pragma unroll
+          for (int qa = o; qa >= 0; --qa)
+            acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[qa][ti], bb[o - qa][tj], acc[ti][tj], 0, 0, 0);
       }
     __syncthreads();
   }
@@ -271,18 +287,28 @@ hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, in
                     float* C, long ldc, long sC, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   dim3 g = gemm_grid(M, N, batch);
-  const int kind = mode == Prec::BF16X3 ? KC_GEMM_BF16X3 : KC_GEMM_F32;
+  const int kind = mode == Prec::BF16X3 ? KC_GEMM_BF16X3 : (mode == Prec::BF16X6 ? KC_GEMM_BF16X6 : KC_GEMM_F32);
   const double fl = 2.0 * M * N * (double)K * batch;
   const double by = 4.0 * batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.f ? 2 : 1));
-  if (mode == Prec::BF16X3) {
-    if (!tA && !tB)
-      launch_timed(kind, fl, by, gemm_bf16x3_kernel<false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-    else if (tA && !tB)
-      launch_timed(kind, fl, by, gemm_bf16x3_kernel<true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-    else if (!tA && tB)
-      launch_timed(kind, fl, by, gemm_bf16x3_kernel<false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-    else
-      launch_timed(kind, fl, by, gemm_bf16x3_kernel<true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  if (mode == Prec::BF16X3 || mode == Prec::BF16X6) {
+    const bool six = mode == Prec::BF16X6;
+#define SPLIT_LAUNCH(TA_, TB_)                                                                                      \
+  if (six)                                                                                                           \
+    launch_timed(kind, fl, by, gemm_bf16s_kernel<TA_, TB_, 3>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, \
+                 sB, beta, C, ldc, sC);                                                                              \
+  else                                                                                                               \
+    launch_timed(kind, fl, by, gemm_bf16s_kernel<TA_, TB_, 2>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, \
+                 sB, beta, C, ldc, sC);
+    if (!tA && !tB) {
+      SPLIT_LAUNCH(false, false)
+    } else if (tA && !tB) {
+      SPLIT_LAUNCH(true, false)
+    } else if (!tA && tB) {
+      SPLIT_LAUNCH(false, true)
+    } else {
+      SPLIT_LAUNCH(true, true)
+    }
+#undef SPLIT_LAUNCH
     return hipGetLastError();
   }
   if (!tA && !tB)

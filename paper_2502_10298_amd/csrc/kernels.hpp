@@ -8,7 +8,7 @@
 
 namespace sctm {
 
-enum class Prec : int { F64 = 0, F32 = 1, BF16X3 = 2 };
+enum class Prec : int { F64 = 0, F32 = 1, BF16X3 = 2, BF16X6 = 3 };
 
 // C[M,N] = alpha * op(A)[M,K] * op(B)[K,N] + beta * C, all row-major.
 // transA: A is stored K x M (leading dimension lda); else M x K.

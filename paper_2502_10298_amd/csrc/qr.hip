@@ -51,48 +51,31 @@ static QrLayout qr_layout(int m, int k, int batch) {
 
 size_t qr_work_bytes(int m, int k, int batch) { return qr_layout(m, k, batch).total; }
 
-// Block-wide sum of NV values per thread over NW wavefronts; red: LDS
-// scratch of NW * NV doubles; the sums land in out[0 .. NV-1] (LDS) for every
-// thread to read.
-template <int NW, int NV>
-__device__ inline void block_sum(double (&v)[NV], double* red, double* out) {
-  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    double a = v[q];
-    for (int w = 32; w > 0; w >>= 1) a += __shfl_xor(a, w);
-    v[q] = a;
-  }
-  if (l == 0)
-#pragma unroll
-    for (int q = 0; q < NV; ++q) red[wv * NV + q] = v[q];
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    double a = 0.0;
-    for (int w = 0; w < NW; ++w) a += red[w * NV + threadIdx.x];
-    out[threadIdx.x] = a;
-  }
-  __syncthreads();
-}
-
 // Factor the panel of columns p0 .. p0 + w - 1 (rows p0 .. m - 1) of every
 // matrix; writes the reflectors (below the diagonal) and R (on and above it)
 // back into Xt, the reflectors as full rows into Vr (zeros above, 1 on the
 // diagonal) and the panel's T.  NT threads, RM rows per thread
 // (m - p0 <= NT RM), PWT columns.
+//
+// One block-wide reduction per column: with v = [1; x_below scale] every dot
+// product the step needs follows from the raw sums s_l = sum_{i > c} x_ij x_il
+// and the diagonal row c, d_l = x_cl + scale s_l: for l > j the coefficient of
+// the update of column l, for l < j the entry v_l . v_j of T's recurrence,
+// and s_j = |x_below|^2.  The sums go through LDS in two stages.
 template <int NT, int RM, int PWT>
 __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr_all, double* T_all, int m, int k,
-                                                        long sX, long sT, int p0) {
+                                                      long sX, long sT, int p0) {
+  constexpr int NSEG = NT / PWT;   // stage-2 segments of PWT partial rows each
   const int b = blockIdx.x;
   double* Xt = Xt_all + b * sX;
   double* Vr = Vr_all + b * sX;
   double* Tp = T_all + b * sT + (long)(p0 / TSLOT) * PW * PW;
   const int w = min(PWT, k - p0);
   const int t = threadIdx.x;
-  constexpr int NW = NT / 64;   // wavefronts
-  __shared__ double red[NW * PW];
-  __shared__ double dots[PW];
-  __shared__ double x0s;
+  __shared__ double buf[NT][PWT + 1];
+  __shared__ double seg[NSEG][PWT + 1];
+  __shared__ double S[PWT];
+  __shared__ double rowc[2][PWT];
   __shared__ double Ts[PW][PW];
   double x[RM][PWT];
 #pragma unroll
@@ -101,84 +84,81 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
 #pragma unroll
     for (int l = 0; l < PWT; ++l) x[r][l] = (i < m && l < w) ? Xt[(long)(p0 + l) * m + i] : 0.0;
   }
-  if (t < PW * PW) Ts[t / PW][t % PW] = 0.0;
+  for (int e = t; e < PW * PW; e += NT) Ts[e / PW][e % PW] = 0.0;
   __syncthreads();
   for (int j = 0; j < w; ++j) {
     const int c = p0 + j;
-    // |x below the diagonal|^2 and the diagonal entry
-    double ss[1] = {0.0};
+    double* rc = rowc[j & 1];
+    // partial sums over this thread's rows below the diagonal; the owner of
+    // row c publishes it
+    double part[PWT];
+#pragma unroll
+    for (int l = 0; l < PWT; ++l) part[l] = 0.0;
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
       const int i = p0 + t + NT * r;
+      double xj = 0.0;
 #pragma unroll
       for (int l = 0; l < PWT; ++l)
-        if (l == j) {
-          if (i > c && i < m) ss[0] += x[r][l] * x[r][l];
-          if (i == c) x0s = x[r][l];
-        }
+        if (l == j) xj = x[r][l];
+      if (i > c && i < m) {
+#pragma unroll
+        for (int l = 0; l < PWT; ++l) part[l] += xj * x[r][l];
+      }
+      if (i == c) {
+#pragma unroll
+        for (int l = 0; l < PWT; ++l) rc[l] = x[r][l];
+      }
     }
-    block_sum<NW, 1>(ss, red, dots);
-    const double sq = dots[0], x0 = x0s;
+#pragma unroll
+    for (int l = 0; l < PWT; ++l) buf[t][l] = part[l];
+    __syncthreads();
+    {
+      const int l = t % PWT, g = t / PWT;
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < PWT; ++q) a += buf[g * PWT + q][l];
+      seg[g][l] = a;
+    }
+    __syncthreads();
+    if (t < PWT) {
+      double a = 0.0;
+      for (int g = 0; g < NSEG; ++g) a += seg[g][t];
+      S[t] = a;
+    }
+    __syncthreads();
+    const double sq = S[j], x0 = rc[j];
     double tau = 0.0, beta = x0, scale = 0.0;
     if (sq > 0.0) {
       beta = -copysign(sqrt(x0 * x0 + sq), x0);
       tau = (beta - x0) / beta;
       scale = 1.0 / (x0 - beta);
     }
-    // v (v_c = 1 implicit) into column j; R entry on the diagonal
-    double vi[RM];
+    // v into column j (R entry on the diagonal), then H_j on columns l > j
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
       const int i = p0 + t + NT * r;
+      double vi = 0.0;
 #pragma unroll
       for (int l = 0; l < PWT; ++l)
         if (l == j) {
           if (i > c && i < m) x[r][l] *= scale;
           if (i == c) x[r][l] = beta;
-          vi[r] = (i == c) ? 1.0 : ((i > c && i < m) ? x[r][l] : 0.0);
+          vi = (i == c) ? 1.0 : ((i > c && i < m) ? x[r][l] : 0.0);
         }
+#pragma unroll
+      for (int l = 0; l < PWT; ++l)
+        if (l > j) x[r][l] -= tau * (rc[l] + scale * S[l]) * vi;
     }
-    // d_l = v . x_l for the panel columns (l > j: to update; l < j: v_l . v_j
-    // for T), reduced one column at a time (one live partial per thread)
-    {
-      const int ln = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-      for (int l = 0; l < PWT; ++l) {
-        double a = 0.0;
-#pragma unroll
-        for (int r = 0; r < RM; ++r) {
-          const int i = p0 + t + NT * r;
-          // column l < j holds v_l below its diagonal p0 + l (< c): rows >= c carry v_l values
-          a += vi[r] * ((l < j) ? ((i == p0 + l) ? 1.0 : x[r][l]) : x[r][l]);
-        }
-        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-        if (ln == 0) red[wv * PWT + l] = a;
-      }
-      __syncthreads();
-      if (t < PWT) {
-        double a = 0.0;
-        for (int q = 0; q < NW; ++q) a += red[q * PWT + t];
-        dots[t] = a;
-      }
-      __syncthreads();
-    }
-    // apply H_j to the remaining panel columns
-#pragma unroll
-    for (int l = 0; l < PWT; ++l)
-      if (l > j) {
-        const double f = tau * dots[l];
-#pragma unroll
-        for (int r = 0; r < RM; ++r) x[r][l] -= f * vi[r];
-      }
-    // T column j:  T[0:j, j] = -tau T[0:j, 0:j] z,  z_q = v_q . v_j
+    // T column j:  T[0:j, j] = -tau T[0:j, 0:j] z,  z_q = v_q . v_j = d_q
     if (t < j) {
       double a = 0.0;
-      for (int q = t; q < j; ++q) a += Ts[t][q] * dots[q];
+      for (int q = t; q < j; ++q) a += Ts[t][q] * (rc[q] + scale * S[q]);
       Ts[t][j] = -tau * a;
     }
     if (t == j) Ts[j][j] = tau;
-    __syncthreads();
   }
+  __syncthreads();
   // write back: Xt rows p0 .. p0 + w - 1, the reflector rows, T
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
@@ -194,7 +174,7 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
   // rows of Vr before p0 are zero (the reflectors act on rows >= p0 + l)
   for (int l = 0; l < w; ++l)
     for (int i = t; i < p0; i += NT) Vr[(long)(p0 + l) * m + i] = 0.0;
-  if (t < PW * PW) Tp[t] = Ts[t / PW][t % PW];
+  for (int e = t; e < PW * PW; e += NT) Tp[e] = Ts[e / PW][e % PW];
 }
 
 // Y <- Y - ((Y V) T') V^T for the rows of Y (nt rows of length len, leading

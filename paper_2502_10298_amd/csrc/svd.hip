@@ -183,15 +183,23 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(const double* Gt_all, 
 
 // Jacobi rotation that zeroes the (a, c) entry of a symmetric 2 x 2 block:
 // new row a = c row_a - s row_c, new row c = s row_a + c row_c (same on
-// columns).  Below the threshold the identity is returned.
+// columns).  Below the threshold the identity is returned.  With D = h_cc -
+// h_aa and E = 2 h_ac the tangent of the smaller angle is
+// t = sign(D E) |E| / (|D| + sqrt(D^2 + E^2)), and c = 1 / sqrt(1 + t^2) comes
+// from the hardware reciprocal square root refined by two Newton steps
+// (c^2 + s^2 = 1 to working accuracy, which keeps W orthogonal).
 __device__ inline void jacobi_rot(double haa, double hcc, double hac, double thr, double negl2, double& c, double& s) {
   c = 1.0;
   s = 0.0;
-  if (fabs(hac) > thr * sqrt(fmax(haa, negl2)) * sqrt(fmax(hcc, negl2))) {
-    const double zeta = (hcc - haa) / (2.0 * hac);
-    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    c = 1.0 / sqrt(1.0 + t * t);
-    s = c * t;
+  if (hac * hac > thr * thr * fmax(haa, negl2) * fmax(hcc, negl2)) {
+    const double D = hcc - haa, E = 2.0 * hac;
+    const double t = ((D >= 0.0) == (E >= 0.0) ? 1.0 : -1.0) * fabs(E) / (fabs(D) + sqrt(D * D + E * E));
+    const double x = 1.0 + t * t;
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    c = y;
+    s = y * t;
   }
 }
 

@@ -20,7 +20,8 @@ enum KernelClass : int {
   KC_JACOBI_GRAM = 3,
   KC_JACOBI_SOLVE = 4,
   KC_JACOBI_ROTATE = 5,
-  KC_COUNT = 6
+  KC_GEMM_BF16X6 = 6,
+  KC_COUNT = 7
 };
 
 struct KernelTimer {

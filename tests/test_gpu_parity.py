@@ -26,7 +26,7 @@ def _say(*a):
 # ---------------------------------------------------------------------------
 # kernels
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16x3", 4e-5), ("bf16x6", 2e-6)])
 @pytest.mark.parametrize("shape", [(70, 45, 33), (300, 260, 190), (1, 129, 64), (257, 3, 1000)])
 @pytest.mark.parametrize("tA,tB", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm(prec, tol, shape, tA, tB):
@@ -42,7 +42,7 @@ def test_gemm(prec, tol, shape, tA, tB):
     assert err < tol, float(err)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16x3", 4e-5), ("bf16x6", 2e-6)])
 @pytest.mark.parametrize("shape", [(64, 96, 20000), (130, 7, 8193), (1, 1, 65536), (200, 100, 1500)])
 @pytest.mark.parametrize("tA,tB", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm_split_k(prec, tol, shape, tA, tB):
@@ -225,11 +225,45 @@ def test_gradient_checkpoint_blocks_agree():
         assert torch.allclose(g, out[0][1], atol=1e-11 * float(out[0][1].abs().max()))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5)])
+@pytest.fixture(scope="module")
+def converged_env_d2_chi8():
+    """The oracle's own environment of the d2_D2_chi8 workload after 20
+    sweeps from the identity boundary (a well-conditioned start)."""
+    A_np = inp.workload_peps("d2_D2_chi8")
+    env, _ = _oracle_run(A_np, 8, 20)
+    return A_np, {k: {n: t.detach().numpy().copy() for n, t in e.items()} for k, e in env.items()}
+
+
+@pytest.mark.parametrize("prec,etol,gtol", [("fp64", 1e-10, 1e-8), ("fp32", 1e-6, 1e-5), ("bf16x6", 1e-6, 1e-5),
+                                            ("bf16x3", 5e-5, 5e-4)])
+def test_mixed_precision_gradient(prec, etol, gtol, converged_env_d2_chi8):
+    """Energy and dE/dA (2 sweeps from a converged start, D=2, chi=8) with
+    FP32 / BF16x6 contractions and FP64 projectors and decomposition
+    adjoints, against the oracle's autograd gradient: energy to 1e-6 and
+    gradient to 1e-5 relative.  BF16x3 is held to what its 2^-17 operand
+    split allows (5e-5, 5e-4)."""
+    A_np, env0 = converged_env_d2_chi8
+    chi, ns = 8, 2
+    h = inp.heisenberg_h_rotated()
+    _say("gradient d2 chi8 from a converged start", prec)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec=prec, with_grad=True, n_sweeps=ns, ckpt_every=1)
+    obj.env_import(torch.tensor(inp.pack_env(env0, 1, 1, 2, chi, chi), device=DEV))
+    e_gpu, dA = obj.energy_grad(h, ns, 1)
+    e_ref, g_ref = og.energy_and_grad(A_np, env0, chi, chi, ns, h)
+    g = dA.cpu().numpy()
+    eerr = abs(e_gpu - e_ref) / abs(e_ref)
+    gerr = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"[result] {prec}: energy rel err {eerr:.2e}, gradient rel err {gerr:.2e}", flush=True)
+    assert eerr <= etol, eerr
+    assert gerr <= gtol, gerr
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x6", 1e-6), ("bf16x3", 5e-5)])
 def test_mixed_precision_energy(prec, tol):
-    """FP32 contractions with FP64 projectors: energy within 1e-6 relative of
-    the FP64 oracle.  BF16x3 (two-term bf16 split, three products) carries a
-    2^-17 operand error; its measured energy error is about 1.3e-5."""
+    """FP32 contractions and BF16x6 (three-way bf16 split, six products) with
+    FP64 projectors: energy within 1e-6 relative of the FP64 oracle.  BF16x3
+    (two-term split, three products) carries a 2^-17 operand error; its
+    measured energy error is about 1.3e-5."""
     A_np = inp.workload_peps("d2_D2_chi8")
     h = inp.heisenberg_h_rotated()
     _say("energy d2_D2_chi8", prec)
