@@ -721,6 +721,11 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, int n_sweeps, int 
     if (s == 0 && !E.dry && E.ok())
       E.check(hipMemcpyAsync(c->cur_blk.p, src.p, src.bytes(), hipMemcpyDeviceToDevice, E.s));
     for (int dir = 0; dir < 4 && E.ok(); ++dir) {
+      // the inputs of the moves of the last block are kept as they go by: its
+      // reverse pass needs no regeneration
+      if (s >= s_last && !E.dry && E.ok())
+        E.check(hipMemcpyAsync(mv[(s - s_last) * 4 + dir].p, c->cur_blk.p, c->cur_blk.bytes(), hipMemcpyDeviceToDevice,
+                               E.s));
       size_t mk = E.ar.mark();
       E.svdc_select(s >= s_last ? (s - s_last) * 4 + dir : -1, 1);
       Env env = view_env(*c, c->cur_blk);
@@ -788,13 +793,15 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, int n_sweeps, int 
   // ---- reverse over blocks and moves ----
   for (int b = nblk - 1; b >= 0 && E.ok(); --b) {
     const int s0 = b * ckpt, s1 = std::min(n_sweeps, s0 + ckpt);
-    // regenerate the environments at every move of the block (untaped)
+    // regenerate the environments at every move of the block (untaped; the
+    // last block kept them during the forward pass)
     if (!E.dry && E.ok())
       E.check(hipMemcpyAsync(c->cur_blk.p, ck[b].p, ck[b].bytes(), hipMemcpyDeviceToDevice, E.s));
     if (b != nblk - 1)   // the slots hold a later block: re-record (the block's last move recomputes)
       for (auto& sl : E.svdc_slots) sl.valid = false;
     int nm = 0;
-    for (int s = s0; s < s1 && E.ok(); ++s)
+    if (b == nblk - 1) nm = (s1 - s0) * 4;   // inputs kept by the forward pass
+    for (int s = s0; s < s1 && E.ok() && b != nblk - 1; ++s)
       for (int dir = 0; dir < 4 && E.ok(); ++dir) {
         if (!E.dry && E.ok())
           E.check(hipMemcpyAsync(mv[nm].p, c->cur_blk.p, c->cur_blk.bytes(), hipMemcpyDeviceToDevice, E.s));

@@ -45,14 +45,43 @@ __device__ inline f4 mfma_step<float, f4>(float a, float b, f4 c) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 / FP32: BK = 16 (four MFMA k-steps of 4)
+// FP64 / FP32: BK = 32 (eight MFMA k-steps of 4).  The next k tile is loaded
+// into registers while the MFMAs run on the current one in LDS.
 // ---------------------------------------------------------------------------
+template <typename T, bool TA>
+__device__ inline void load_a(const T* __restrict__ A, long lda, int M, int K, int bm, int k0, int tid, T (&r)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if (!TA) {
+      const int row = (tid >> 5) + 8 * i, c = tid & 31, m = bm + row, k = k0 + c;
+      r[i] = (m < M && k < K) ? A[(long)m * lda + k] : T(0);
+    } else {
+      const int row = (tid >> 6) + 4 * i, c = tid & 63, k = k0 + row, m = bm + c;
+      r[i] = (m < M && k < K) ? A[(long)k * lda + m] : T(0);
+    }
+  }
+}
+
+template <typename T, bool TB>
+__device__ inline void load_b(const T* __restrict__ B, long ldb, int N, int K, int bn, int k0, int tid, T (&r)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if (!TB) {
+      const int row = (tid >> 6) + 4 * i, c = tid & 63, k = k0 + row, n = bn + c;
+      r[i] = (n < N && k < K) ? B[(long)k * ldb + n] : T(0);
+    } else {
+      const int row = (tid >> 5) + 8 * i, c = tid & 31, n = bn + row, k = k0 + c;
+      r[i] = (n < N && k < K) ? B[(long)n * ldb + k] : T(0);
+    }
+  }
+}
+
 template <typename T, typename V4, bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
                                                    const T* __restrict__ A, long lda, long sA,
                                                    const T* __restrict__ B, long ldb, long sB, T beta,
                                                    T* __restrict__ C, long ldc, long sC) {
-  constexpr int BK = 16;
+  constexpr int BK = 32;
   __shared__ T As[BK][BM + 4];
   __shared__ T Bs[BK][BN + 4];
   const long bz = blockIdx.z;
@@ -68,40 +97,24 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
+  T ra[8], rb[8];
+  load_a<T, TA>(A, lda, M, K, bm, 0, tid, ra);
+  load_b<T, TB>(B, ldb, N, K, bn, 0, tid, rb);
   for (int k0 = 0; k0 < K; k0 += BK) {
-    if (!TA) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int r = (tid >> 4) + 16 * i, c = tid & 15;
-        int m = bm + r, k = k0 + c;
-        As[c][r] = (m < M && k < K) ? A[(long)m * lda + k] : T(0);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int r = (tid >> 6) + 4 * i, c = tid & 63;
-        int k = k0 + r, m = bm + c;
-        As[r][c] = (m < M && k < K) ? A[(long)k * lda + m] : T(0);
-      }
-    }
-    if (!TB) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int r = (tid >> 6) + 4 * i, c = tid & 63;
-        int k = k0 + r, n = bn + c;
-        Bs[r][c] = (n < N && k < K) ? B[(long)k * ldb + n] : T(0);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int r = (tid >> 4) + 16 * i, c = tid & 15;
-        int n = bn + r, k = k0 + c;
-        Bs[c][r] = (n < N && k < K) ? B[(long)n * ldb + k] : T(0);
-      }
+    for (int i = 0; i < 8; ++i) {
+      if (!TA) As[tid & 31][(tid >> 5) + 8 * i] = ra[i];
+      else As[(tid >> 6) + 4 * i][tid & 63] = ra[i];
+      if (!TB) Bs[(tid >> 6) + 4 * i][tid & 63] = rb[i];
+      else Bs[tid & 31][(tid >> 5) + 8 * i] = rb[i];
     }
     __syncthreads();
+    if (k0 + BK < K) {   // next tile in flight during the MFMAs
+      load_a<T, TA>(A, lda, M, K, bm, k0 + BK, tid, ra);
+      load_b<T, TB>(B, ldb, N, K, bn, k0 + BK, tid, rb);
+    }
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
+    for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
       T a0 = As[kr][wm * 32 + (lane & 15)];
       T a1 = As[kr][wm * 32 + 16 + (lane & 15)];
@@ -174,48 +187,38 @@ __global__ __launch_bounds__(256) void gemm_bf16s_kernel(int M, int N, int K, fl
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
 
+  // the next k tile is loaded into registers while the MFMAs run on the
+  // current one in LDS
+  float ra[8], rb[8];
+  load_a<float, TA>(A, lda, M, K, bm, 0, tid, ra);
+  load_b<float, TB>(B, ldb, N, K, bn, 0, tid, rb);
   for (int k0 = 0; k0 < K; k0 += BK) {
     __bf16 sp[NS];
-    // A panel: 64 rows (m) x 32 k = 2048 values, 8 per thread
-    if (!TA) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        int r = (tid >> 5) + 8 * i, c = tid & 31;
-        int m = bm + r, k = k0 + c;
-        split_bf16<NS>((m < M && k < K) ? A[(long)m * lda + k] : 0.f, sp);
+    for (int i = 0; i < 8; ++i) {
+      // A: m-major rows of k;  B: n-major rows of k (same element mapping as the loads)
+      split_bf16<NS>(ra[i], sp);
+      if (!TA) {
 #pragma unroll
-        for (int q = 0; q < NS; ++q) As[q][r][c] = sp[q];
+        for (int q = 0; q < NS; ++q) As[q][(tid >> 5) + 8 * i][tid & 31] = sp[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) As[q][tid & 63][(tid >> 6) + 4 * i] = sp[q];
       }
-    } else {
+      split_bf16<NS>(rb[i], sp);
+      if (!TB) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        int r = (tid >> 6) + 4 * i, c = tid & 63;   // r = k, c = m
-        int k = k0 + r, m = bm + c;
-        split_bf16<NS>((m < M && k < K) ? A[(long)k * lda + m] : 0.f, sp);
+        for (int q = 0; q < NS; ++q) Bs[q][tid & 63][(tid >> 6) + 4 * i] = sp[q];
+      } else {
 #pragma unroll
-        for (int q = 0; q < NS; ++q) As[q][c][r] = sp[q];
-      }
-    }
-    if (!TB) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        int r = (tid >> 6) + 4 * i, c = tid & 63;   // r = k, c = n
-        int k = k0 + r, n = bn + c;
-        split_bf16<NS>((n < N && k < K) ? B[(long)k * ldb + n] : 0.f, sp);
-#pragma unroll
-        for (int q = 0; q < NS; ++q) Bs[q][c][r] = sp[q];
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        int r = (tid >> 5) + 8 * i, c = tid & 31;   // r = n, c = k
-        int n = bn + r, k = k0 + c;
-        split_bf16<NS>((n < N && k < K) ? B[(long)n * ldb + k] : 0.f, sp);
-#pragma unroll
-        for (int q = 0; q < NS; ++q) Bs[q][r][c] = sp[q];
+        for (int q = 0; q < NS; ++q) Bs[q][(tid >> 5) + 8 * i][tid & 31] = sp[q];
       }
     }
     __syncthreads();
+    if (k0 + BK < K) {
+      load_a<float, TA>(A, lda, M, K, bm, k0 + BK, tid, ra);
+      load_b<float, TB>(B, ldb, N, K, bn, k0 + BK, tid, rb);
+    }
     const int kq = 8 * (lane >> 4);
     bf8 a[NS][2], bb[NS][2];
 #pragma unroll
