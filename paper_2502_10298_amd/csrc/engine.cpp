@@ -758,7 +758,15 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
     void* qwork = ar.alloc(qr_work_bytes((int)nb, (int)rk, 2 * (int)g));
     if (!dry && ok()) {
       const long rr = rk * rk;
+      static const bool qtrace = getenv("SPLITCTM_SVD_TRACE") != nullptr;
+      auto q0 = std::chrono::steady_clock::now();
+      if (qtrace) check(hipStreamSynchronize(s));
       check(qr_f64(s, (int)nb, (int)rk, 2 * (int)g, G.Xq.f64(), G.Rq.f64(), G.Qq.f64(), qwork));
+      if (qtrace && ok()) {
+        check(hipStreamSynchronize(s));
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q0).count();
+        fprintf(stderr, "[qr] m=%ld k=%ld batch=%ld %.1f ms\n", nb, rk, 2 * g, ms);
+      }
       check(gemm_f64(s, false, true, (int)rk, (int)rk, (int)rk, 1.0, G.Rq.f64(), rk, rr, G.Rq.f64() + g * rr, rk, rr,
                      0.0, jM[rk].f64() + G.job0 * rr, rk, rr, (int)g));
     }

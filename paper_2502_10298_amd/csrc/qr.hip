@@ -2,18 +2,24 @@
 // Xt = X^T row-major (row j of Xt = column j of X, contiguous), with the
 // explicit thin factor Q (m x k, also stored transposed) and R (k x k).
 //
-// Blocked right-looking Householder with panels of 16, 8 or 4 columns (as
-// many as the rows held per thread allow without register spills):
+// Two-level blocked right-looking Householder:
+//   outer blocks of NBW = 64 columns; inside a block, panels of 16, 8 or 4
+//   columns (as many as the rows held per thread allow without register
+//   spills):
 //   panel:    one workgroup per matrix factors the panel in registers
 //             (thread t holds rows p0 + t + NT r), one reflector
 //             per column (LAPACK's dlarfg convention: beta = -sign(x0) |x|,
 //             tau = (beta - x0) / beta, v = x / (x0 - beta) with v_0 = 1) and
-//             builds the triangular factor T of the block reflector
-//             H_1 ... H_PW = I - V T V^T (forward, columnwise);
-//   trailing: X_trail <- H^T X_trail, i.e. Xt_trail <- Xt_trail - (Xt_trail V) T V^T,
-//             one fused kernel on the matrix cores;
-//   Q:        Q = H_1 ... H_p [I; 0], accumulated backwards over the panels,
-//             Qt <- Qt - (Qt V) T^T V^T on the trailing block, the same kernel.
+//             builds the triangular factor T of the panel's block reflector
+//             H_1 ... H_pw = I - V T V^T (forward, columnwise);
+//   in-block: the rest of the outer block <- H^T (rest), one fused kernel;
+//   block:    the block's T (64 x 64) from S = V^T V and the taus
+//             (T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] S[0:i, i]), and
+//             the columns beyond the block <- H^T (columns) in two
+//             full-chip kernels on the matrix cores: W = Xt_trail V, then
+//             Xt_trail <- Xt_trail - (W T) V^T;
+//   Q:        Q = H_1 ... H_k [I; 0], accumulated backwards over the outer
+//             blocks with T^T, by the same two kernels.
 // Householder QR is backward stable: Q is orthonormal to working accuracy
 // and X = Q R + dX with |dX| ~ eps |X|, whatever the rank of X.
 #include "kernels.hpp"
@@ -26,10 +32,12 @@ namespace sctm {
 
 static constexpr int PW = 16;     // widest panel (T blocks are PW x PW)
 static constexpr int TSLOT = 4;   // narrowest panel: one T block per TSLOT columns
+static constexpr int NBW = 64;    // columns per outer block
 
 struct QrLayout {
-  long sX, sT;
-  size_t offV, offT, total;
+  long sX, sT, sTB, sW, sP, sTau;
+  int nch;
+  size_t offV, offT, offTB, offW, offW2, offP, offTau, total;
 };
 
 static QrLayout qr_layout(int m, int k, int batch) {
@@ -43,8 +51,19 @@ static QrLayout qr_layout(int m, int k, int batch) {
     off += (bytes + 255) & ~size_t(255);
     return o;
   };
+  const int nblk = (k + NBW - 1) / NBW;
+  L.sTB = (long)nblk * NBW * NBW;
+  L.sW = (long)k * NBW;
+  L.nch = (m + 127) / 128;
+  L.sP = (long)L.nch * NBW * NBW;
+  L.sTau = k;
   L.offV = take(sizeof(double) * L.sX * batch);                // reflectors as rows [k][m]
   L.offT = take(sizeof(double) * L.sT * batch);                // T of every panel
+  L.offTB = take(sizeof(double) * L.sTB * batch);              // T of every outer block
+  L.offW = take(sizeof(double) * L.sW * batch);                // W = Y V of a block update
+  L.offW2 = take(sizeof(double) * L.sW * batch);               // W T
+  L.offP = take(sizeof(double) * L.sP * batch);                // chunk partials of S or of an in-block W
+  L.offTau = take(sizeof(double) * L.sTau * batch);            // tau of every reflector
   L.total = off;
   return L;
 }
@@ -63,8 +82,8 @@ size_t qr_work_bytes(int m, int k, int batch) { return qr_layout(m, k, batch).to
 // the update of column l, for l < j the entry v_l . v_j of T's recurrence,
 // and s_j = |x_below|^2.  The sums go through LDS in two stages.
 template <int NT, int RM, int PWT>
-__global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr_all, double* T_all, int m, int k,
-                                                      long sX, long sT, int p0) {
+__global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr_all, double* T_all,
+                                                      double* tau_all, int m, int k, long sX, long sT, int p0) {
   constexpr int NSEG = NT / PWT;   // stage-2 segments of PWT partial rows each
   const int b = blockIdx.x;
   double* Xt = Xt_all + b * sX;
@@ -156,7 +175,10 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
       for (int q = t; q < j; ++q) a += Ts[t][q] * (rc[q] + scale * S[q]);
       Ts[t][j] = -tau * a;
     }
-    if (t == j) Ts[j][j] = tau;
+    if (t == j) {
+      Ts[j][j] = tau;
+      tau_all[(long)b * k + c] = tau;
+    }
   }
   __syncthreads();
   // write back: Xt rows p0 .. p0 + w - 1, the reflector rows, T
@@ -177,83 +199,146 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
   for (int e = t; e < PW * PW; e += NT) Tp[e] = Ts[e / PW][e % PW];
 }
 
-// Y <- Y - ((Y V) T') V^T for the rows of Y (nt rows of length len, leading
-// dimension ld), V^T = the panel's reflectors (pw <= 16 rows of length len,
-// leading dimension ld) and T' = T (trailing update of the factorisation) or
-// T^T (accumulation of Q).  One workgroup per 16 rows of Y: the four
-// wavefronts split the length for Y V (MFMA, partial products summed in LDS
-// in a fixed order), form (Y V) T' in LDS, then split the column tiles of
-// the rank-pw update (MFMA again).  v_mfma_f64_16x16x4: A lane l holds
+// Partial products over chunks of the column length:
+//   P[ch] = A[:, chunk] B[:, chunk]^T   (A: na <= 64 rows, B: nb rows, both of
+//   length len and leading dimension ld; chunk ch = entries SCH ch .. SCH ch + SCH - 1),
+// written as 64 x 64 row-major tiles.  SAME: B = A (nb = na, the Gram matrix
+// S = V V^T of an outer block's reflectors; only the tiles on and above the
+// diagonal are formed); else nb <= 16 (W = Y V^T of an in-block update).
+// Operands are staged through LDS with coalesced loads; wave w forms the
+// 16-row strip w on the FP64 matrix cores (v_mfma_f64_16x16x4: A lane l holds
 // A[l%16][l/16], B lane l holds B[l/16][l%16], D lane l register r holds
-// D[4r + l/16][l%16]; in Y V lane l takes the summation index
-// k = kb + 16 (l/16) + j at step j, so that each lane streams 16 consecutive
-// entries of its row of Y and of V.
-template <bool TRANS_T>
-__global__ __launch_bounds__(256) void qr_update_kernel(double* Y_all, long sY, int nt, int len, int ld,
-                                                        const double* V_all, long sV, const double* T_all, long sT,
-                                                        int pw) {
+// D[4r + l/16][l%16]).
+static constexpr int SCH = 128;
+
+template <bool SAME>
+__global__ __launch_bounds__(256) void qr_rowprod_partial_kernel(const double* A_all, long sA, int na,
+                                                                 const double* B_all, long sB, int nb, int len,
+                                                                 int ld, double* P_all, int nch) {
   typedef double d4u __attribute__((ext_vector_type(4)));
+  constexpr int NBR = SAME ? NBW : 16;
+  const int b = blockIdx.y, ch = blockIdx.x;
+  const double* A = A_all + b * sA;
+  const double* B = B_all + b * sB;
+  double* P = P_all + ((long)b * nch + ch) * NBW * NBW;
+  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
+  const int c0 = ch * SCH;
+  __shared__ double As[NBW][SCH + 1];
+  __shared__ double Bs[SAME ? 1 : NBR][SCH + 1];
+  for (int e = tid; e < NBW * SCH; e += 256) {
+    const int r = e / SCH, c = e % SCH;
+    As[r][c] = (r < na && c0 + c < len) ? A[(long)r * ld + c0 + c] : 0.0;
+  }
+  if (!SAME)
+    for (int e = tid; e < NBR * SCH; e += 256) {
+      const int r = e / SCH, c = e % SCH;
+      Bs[r][c] = (r < nb && c0 + c < len) ? B[(long)r * ld + c0 + c] : 0.0;
+    }
+  __syncthreads();
+  if (wv * 16 >= na) return;   // no rows for this wave (uniform)
+  const int ntile = SAME ? NBW / 16 : 1;
+  for (int tj = SAME ? wv : 0; tj < ntile; ++tj) {
+    if (tj * 16 >= nb) break;
+    d4u d = {0, 0, 0, 0};
+#pragma unroll 8
+    for (int kk = 0; kk < SCH / 4; ++kk) {
+      const int kc = 4 * kk + (l >> 4);
+      const double av = As[wv * 16 + (l & 15)][kc];
+      const double bv = SAME ? As[tj * 16 + (l & 15)][kc] : Bs[l & 15][kc];
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) P[(wv * 16 + 4 * r + (l >> 4)) * NBW + tj * 16 + (l & 15)] = d[r];
+  }
+}
+
+// T of an outer block (nv <= NBW reflectors) from S = V V^T (the sum of the
+// chunk partials, fixed order) and the taus, by pairwise merging of adjacent
+// diagonal blocks: H_a H_c = I - [V_a V_c] [[T_aa, T_ac], [0, T_cc]] [V_a V_c]^T
+// with T_ac = -T_aa S_ac T_cc, from 1 x 1 blocks (T_ii = tau_i) up to nv.
+// T is written NBW x NBW (zero below the diagonal and beyond nv).
+__global__ __launch_bounds__(256) void qr_tblock_kernel(const double* P_all, int nch, int nv, const double* tau_all,
+                                                        long sTau, double* TB_all, long sTB) {
+  const int b = blockIdx.x;
+  const double* P = P_all + (long)b * nch * NBW * NBW;
+  const double* tau = tau_all + b * sTau;
+  double* TB = TB_all + b * sTB;
+  __shared__ double Ss[NBW][NBW + 1];
+  __shared__ double Tm[NBW][NBW + 1];
+  __shared__ double X[NBW][NBW + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NBW * NBW; e += 256) {
+    const int r = e / NBW, c = e % NBW;
+    double a = 0.0;
+    if (r / 16 <= c / 16 && r < nv && c < nv)
+      for (int ch = 0; ch < nch; ++ch) a += P[(long)ch * NBW * NBW + e];
+    Ss[r][c] = a;
+    Tm[r][c] = (r == c && r < nv) ? tau[r] : 0.0;
+  }
+  __syncthreads();
+  for (int h = 1; h < NBW; h *= 2) {
+    const int nent = (NBW / (2 * h)) * h * h;
+    for (int e = tid; e < nent; e += 256) {
+      const int s0 = 2 * h * (e / (h * h)), ii = (e / h) % h, jj = e % h;
+      double a = 0.0;
+      for (int q = 0; q <= jj; ++q) a += Ss[s0 + ii][s0 + h + q] * Tm[s0 + h + q][s0 + h + jj];
+      X[s0 + ii][s0 + h + jj] = a;
+    }
+    __syncthreads();
+    for (int e = tid; e < nent; e += 256) {
+      const int s0 = 2 * h * (e / (h * h)), ii = (e / h) % h, jj = e % h;
+      double a = 0.0;
+      for (int q = ii; q < h; ++q) a += Tm[s0 + ii][s0 + q] * X[s0 + q][s0 + h + jj];
+      Tm[s0 + ii][s0 + h + jj] = -a;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NBW * NBW; e += 256) TB[e] = Tm[e / NBW][e % NBW];
+}
+
+// In-block update: Y <- Y - (W T) V for the nt <= 64 rows of Y (length len,
+// leading dimension ld), V the panel's pw <= 16 reflector rows, T its
+// triangular factor (PW x PW) and W = Y V^T the sum of the chunk partials.
+// One workgroup per 256 entries of the length (thread = one entry).
+__global__ __launch_bounds__(256) void qr_inblock_apply_kernel(double* Y_all, long sY, int nt, int len, int ld,
+                                                               const double* V_all, long sV, int pw,
+                                                               const double* P_all, int nch, const double* T_all,
+                                                               long sT) {
   const int b = blockIdx.y;
   double* Y = Y_all + b * sY;
   const double* V = V_all + b * sV;
+  const double* P = P_all + (long)b * nch * NBW * NBW;
   const double* T = T_all + b * sT;
-  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
-  const int row0 = blockIdx.x * 16;
+  const int tid = threadIdx.x;
+  __shared__ double Wm[NBW][PW + 1];
+  __shared__ double W2[NBW][PW + 1];
   __shared__ double Ts[PW][PW + 1];
-  __shared__ double red[4][16][17];
-  __shared__ double w2[16][PW + 1];
-  for (int e = tid; e < PW * PW; e += 256) Ts[e / PW][e % PW] = T[e];
-  // partial W1 = Y V over the wave's quarter of the length (64-entry blocks)
-  const int nblk = (len + 63) / 64;
-  const int ra = row0 + (l & 15);
-  const bool rok = ra < nt, vok = (l & 15) < pw;
-  const double* yrow = Y + (long)ra * ld;
-  const double* vrow = V + (long)(l & 15) * ld;
-  d4u d = {0, 0, 0, 0};
-  for (int blk = wv; blk < nblk; blk += 4) {
-    const int k0 = blk * 64 + 16 * (l >> 4);
-    double av[16], bv[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int kk = k0 + j;
-      av[j] = (rok && kk < len) ? yrow[kk] : 0.0;
-      bv[j] = (vok && kk < len) ? vrow[kk] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < 16; ++j) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], d, 0, 0, 0);
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) red[wv][4 * r + (l >> 4)][l & 15] = d[r];
-  __syncthreads();
-  // W2 = W1 T'  (16 x pw), W1 = sum of the four partials
-  {
-    const int i = tid >> 4, c = tid & 15;
+  for (int e = tid; e < NBW * PW; e += 256) {
+    const int r = e / PW, c = e % PW;
     double a = 0.0;
-    for (int j = 0; j < pw; ++j) {
-      const double w1 = (red[0][i][j] + red[1][i][j]) + (red[2][i][j] + red[3][i][j]);
-      a += w1 * (TRANS_T ? Ts[c][j] : Ts[j][c]);
-    }
-    w2[i][c] = (c < pw) ? a : 0.0;
+    if (r < nt && c < pw)
+      for (int ch = 0; ch < nch; ++ch) a += P[(long)ch * NBW * NBW + r * NBW + c];
+    Wm[r][c] = a;
+  }
+  for (int e = tid; e < PW * PW; e += 256) Ts[e / PW][e % PW] = T[e];
+  __syncthreads();
+  for (int e = tid; e < NBW * PW; e += 256) {
+    const int r = e / PW, c = e % PW;
+    double a = 0.0;
+    for (int j = 0; j < pw; ++j) a += Wm[r][j] * Ts[j][c];
+    W2[r][c] = (c < pw) ? a : 0.0;
   }
   __syncthreads();
-  // Y -= W2 V^T, the waves taking 16-column tiles in turn
-  const int nk = (pw + 3) / 4;
-  for (int i0 = wv * 16; i0 < len; i0 += 64) {
-    const int ci = i0 + (l & 15);
-    d4u u = {0, 0, 0, 0};
-    for (int kk = 0; kk < nk; ++kk) {
-      const int j = kk * 4 + (l >> 4);
-      const double a = (j < pw) ? w2[l & 15][j] : 0.0;
-      const double bb = (j < pw && ci < len) ? V[(long)j * ld + ci] : 0.0;
-      u = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, u, 0, 0, 0);
-    }
-    if (ci < len) {
+  const int i = blockIdx.x * 256 + tid;
+  if (i >= len) return;
+  double v[PW];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rr = row0 + 4 * r + (l >> 4);
-        if (rr < nt) Y[(long)rr * ld + ci] -= u[r];
-      }
-    }
+  for (int c = 0; c < PW; ++c) v[c] = (c < pw) ? V[(long)c * ld + i] : 0.0;
+  for (int r = 0; r < nt; ++r) {
+    double a = 0.0;
+#pragma unroll
+    for (int c = 0; c < PW; ++c) a += W2[r][c] * v[c];
+    Y[(long)r * ld + i] -= a;
   }
 }
 
@@ -287,57 +372,101 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
   char* w = (char*)work;
   double* Vr = (double*)(w + L.offV);
   double* T = (double*)(w + L.offT);
+  double* TB = (double*)(w + L.offTB);
+  double* Wb = (double*)(w + L.offW);
+  double* W2b = (double*)(w + L.offW2);
+  double* Pb = (double*)(w + L.offP);
+  double* tau = (double*)(w + L.offTau);
   hipError_t e = hipSuccess;
-  // panels: 256 threads with up to 4 rows each and 16 columns, or 8 rows
-  // and 8 columns; beyond 2048 rows 1024 threads with 4 columns
+  // panels of 16 columns with 256 threads (up to 4 rows each) or 512 threads
+  // (4 rows each, up to 2048 rows); beyond 2048 rows 1024 threads with 4
+  // columns; no panel crosses an outer block boundary
   struct Panel {
     int p0, pw, nt_threads, rm;
   };
   std::vector<Panel> pans;
   for (int p0 = 0; p0 < k;) {
     const int rows = m - p0;
+    const int bend = std::min(k, (p0 / NBW + 1) * NBW);
     Panel P;
     P.p0 = p0;
-    if (rows <= 2048) {
+    if (rows <= 1024) {
       const int need = (rows + 255) / 256;
       P.nt_threads = 256;
-      P.rm = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
-      P.pw = std::min(P.rm == 8 ? 8 : 16, k - p0);
+      P.rm = need <= 1 ? 1 : need <= 2 ? 2 : 4;
+      P.pw = std::min(16, bend - p0);
+    } else if (rows <= 2048) {
+      P.nt_threads = 512;
+      P.rm = 4;
+      P.pw = std::min(16, bend - p0);
     } else {
       P.nt_threads = 1024;
       P.rm = (rows + 1023) / 1024;
-      P.pw = std::min(4, k - p0);
+      P.pw = std::min(4, bend - p0);
     }
     pans.push_back(P);
     p0 += P.pw;
   }
-  for (const Panel& P : pans) {
-    if (e != hipSuccess) break;
-    const int p0 = P.p0, pw = P.pw, rows = m - p0;
-    const dim3 g(batch);
-    if (P.nt_threads == 256) {
-      if (P.rm == 1)
-        hipLaunchKernelGGL((qr_panel_kernel<256, 1, 16>), g, dim3(256), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
-      else if (P.rm == 2)
-        hipLaunchKernelGGL((qr_panel_kernel<256, 2, 16>), g, dim3(256), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
-      else if (P.rm == 4)
-        hipLaunchKernelGGL((qr_panel_kernel<256, 4, 16>), g, dim3(256), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
-      else
-        hipLaunchKernelGGL((qr_panel_kernel<256, 8, 8>), g, dim3(256), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
-    } else {
-      if (P.rm <= 3)
-        hipLaunchKernelGGL((qr_panel_kernel<1024, 3, 4>), g, dim3(1024), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
-      else
-        hipLaunchKernelGGL((qr_panel_kernel<1024, 4, 4>), g, dim3(1024), 0, s, Xt, Vr, T, m, k, L.sX, L.sT, p0);
+  const int nblk = (k + NBW - 1) / NBW;
+  size_t pi = 0;
+  for (int bi = 0; bi < nblk && e == hipSuccess; ++bi) {
+    const int j0 = bi * NBW, j1 = std::min(k, j0 + NBW), nv = j1 - j0;
+    for (; pi < pans.size() && pans[pi].p0 < j1 && e == hipSuccess; ++pi) {
+      const Panel& P = pans[pi];
+      const int p0 = P.p0, pw = P.pw, rows = m - p0;
+      const dim3 g(batch);
+      if (P.nt_threads == 256) {
+        if (P.rm == 1)
+          hipLaunchKernelGGL((qr_panel_kernel<256, 1, 16>), g, dim3(256), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+        else if (P.rm == 2)
+          hipLaunchKernelGGL((qr_panel_kernel<256, 2, 16>), g, dim3(256), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+        else
+          hipLaunchKernelGGL((qr_panel_kernel<256, 4, 16>), g, dim3(256), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+      } else if (P.nt_threads == 512) {
+        hipLaunchKernelGGL((qr_panel_kernel<512, 4, 16>), g, dim3(512), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+      } else {
+        if (P.rm <= 3)
+          hipLaunchKernelGGL((qr_panel_kernel<1024, 3, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+        else
+          hipLaunchKernelGGL((qr_panel_kernel<1024, 4, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+      }
+      e = hipGetLastError();
+      const int nt = j1 - p0 - pw;   // rest of the outer block (rows of Xt)
+      if (nt <= 0 || e != hipSuccess) continue;
+      // Xt_rest (nt x rows, ld m) -= ((Xt_rest V^T) T) V: chunk partials of W, then the update
+      double* Y = Xt + (long)(p0 + pw) * m + p0;
+      const double* Vp = Vr + (long)p0 * m + p0;
+      const int nch = (rows + SCH - 1) / SCH;
+      hipLaunchKernelGGL(qr_rowprod_partial_kernel<false>, dim3(nch, batch), dim3(256), 0, s, (const double*)Y,
+                         L.sX, nt, Vp, L.sX, pw, rows, m, Pb, nch);
+      e = hipGetLastError();
+      if (e != hipSuccess) break;
+      hipLaunchKernelGGL(qr_inblock_apply_kernel, dim3((rows + 255) / 256, batch), dim3(256), 0, s, Y, L.sX, nt, rows,
+                         m, Vp, L.sX, pw, (const double*)Pb, nch,
+                         (const double*)(T + (long)(p0 / TSLOT) * PW * PW), L.sT);
+      e = hipGetLastError();
     }
+    if (e != hipSuccess) break;
+    // block reflector: T from S = V V^T, then the trailing columns
+    const int nt = k - j1, rows = m - j0;
+    const double* Vb = Vr + (long)j0 * m + j0;
+    const int nch = (rows + SCH - 1) / SCH;
+    hipLaunchKernelGGL(qr_rowprod_partial_kernel<true>, dim3(nch, batch), dim3(256), 0, s, Vb, L.sX, nv, Vb, L.sX, nv,
+                       rows, m, Pb, nch);
     e = hipGetLastError();
-    const int nt = k - p0 - pw;   // trailing columns of X = rows of Xt
+    if (e != hipSuccess) break;
+    double* TBb = TB + (long)bi * NBW * NBW;
+    hipLaunchKernelGGL(qr_tblock_kernel, dim3(batch), dim3(256), 0, s, (const double*)Pb, nch, nv,
+                       (const double*)(tau + j0), L.sTau, TBb, L.sTB);
+    e = hipGetLastError();
     if (nt <= 0 || e != hipSuccess) continue;
-    // Xt_trail (nt x rows, ld m) -= ((Xt_trail V) T) V^T
-    hipLaunchKernelGGL(qr_update_kernel<false>, dim3((nt + 15) / 16, batch), dim3(256), 0, s,
-                       Xt + (long)(p0 + pw) * m + p0, L.sX, nt, rows, m, (const double*)(Vr + (long)p0 * m + p0),
-                       L.sX, (const double*)(T + (long)(p0 / TSLOT) * PW * PW), L.sT, pw);
-    e = hipGetLastError();
+    // Xt_trail (nt x rows) -= ((Xt_trail V^T) T) V
+    double* Y = Xt + (long)j1 * m + j0;
+    e = gemm_f64(s, false, true, nt, nv, rows, 1.0, Y, m, L.sX, Vb, m, L.sX, 0.0, Wb, NBW, L.sW, batch);
+    if (e == hipSuccess)
+      e = gemm_f64(s, false, false, nt, nv, nv, 1.0, Wb, NBW, L.sW, TBb, NBW, L.sTB, 0.0, W2b, NBW, L.sW, batch);
+    if (e == hipSuccess)
+      e = gemm_f64(s, false, false, nt, rows, nv, -1.0, W2b, NBW, L.sW, Vb, m, L.sX, 1.0, Y, m, L.sX, batch);
   }
   if (e != hipSuccess) return e;
   if (R) {
@@ -347,14 +476,18 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
   if (!Qt || e != hipSuccess) return e;
   hipLaunchKernelGGL(qr_eye_kernel, dim3(grid_of((long)k * m), batch), dim3(256), 0, s, Qt, m, k, L.sX);
   e = hipGetLastError();
-  for (int pi = (int)pans.size() - 1; pi >= 0 && e == hipSuccess; --pi) {
-    const int p0 = pans[pi].p0, pw = pans[pi].pw;
-    const int rows = m - p0, nt = k - p0;
-    // Qt_sub (rows p0.., columns p0..) -= ((Qt_sub V) T^T) V^T
-    hipLaunchKernelGGL(qr_update_kernel<true>, dim3((nt + 15) / 16, batch), dim3(256), 0, s,
-                       Qt + (long)p0 * m + p0, L.sX, nt, rows, m, (const double*)(Vr + (long)p0 * m + p0), L.sX,
-                       (const double*)(T + (long)(p0 / TSLOT) * PW * PW), L.sT, pw);
-    e = hipGetLastError();
+  for (int bi = nblk - 1; bi >= 0 && e == hipSuccess; --bi) {
+    const int j0 = bi * NBW, nv = std::min(k, j0 + NBW) - j0;
+    const int rows = m - j0, nt = k - j0;
+    const double* Vb = Vr + (long)j0 * m + j0;
+    const double* TBb = TB + (long)bi * NBW * NBW;
+    double* Y = Qt + (long)j0 * m + j0;
+    // Qt_sub (rows j0.., columns j0..) -= ((Qt_sub V^T) T^T) V
+    e = gemm_f64(s, false, true, nt, nv, rows, 1.0, Y, m, L.sX, Vb, m, L.sX, 0.0, Wb, NBW, L.sW, batch);
+    if (e == hipSuccess)
+      e = gemm_f64(s, false, true, nt, nv, nv, 1.0, Wb, NBW, L.sW, TBb, NBW, L.sTB, 0.0, W2b, NBW, L.sW, batch);
+    if (e == hipSuccess)
+      e = gemm_f64(s, false, false, nt, rows, nv, -1.0, W2b, NBW, L.sW, Vb, m, L.sX, 1.0, Y, m, L.sX, batch);
   }
   return e;
 }

@@ -92,10 +92,12 @@ def test_jacobi_svd(n, batch):
     assert sweeps < 60
 
 
-@pytest.mark.parametrize("m,k,batch", [(40, 17, 1), (300, 150, 3), (2048, 1024, 2), (3200, 160, 1), (64, 64, 2)])
+@pytest.mark.parametrize("m,k,batch", [(40, 17, 1), (300, 150, 3), (2048, 1024, 2), (3200, 160, 1), (64, 64, 2),
+                                       (200, 130, 2), (4096, 300, 1), (1024, 1024, 3)])
 def test_householder_qr(m, k, batch):
     """X = Q R with Q orthonormal and R upper triangular, to working accuracy,
-    on graded and rank-deficient inputs (panels of 16, 8 and 4 columns)."""
+    on graded and rank-deficient inputs (panels of 16, 8 and 4 columns; outer
+    blocks of 64 columns with a ragged last block)."""
     _say("qr", m, k, batch)
     g = torch.Generator().manual_seed(m + k)
     X = torch.randn(batch, m, k, generator=g, dtype=torch.float64)
