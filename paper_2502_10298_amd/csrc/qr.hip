@@ -26,6 +26,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 namespace sctm {
@@ -33,6 +35,12 @@ namespace sctm {
 static constexpr int PW = 16;     // widest panel (T blocks are PW x PW)
 static constexpr int TSLOT = 4;   // narrowest panel: one T block per TSLOT columns
 static constexpr int NBW = 64;    // columns per outer block
+
+// f(integral_constant<int, J>) for J = Js... in order
+template <typename F, int... Js>
+__device__ __forceinline__ void static_for(F& f, std::integer_sequence<int, Js...>) {
+  (f(std::integral_constant<int, Js>{}), ...);
+}
 
 struct QrLayout {
   long sX, sT, sTB, sW, sP, sTau;
@@ -74,7 +82,7 @@ size_t qr_work_bytes(int m, int k, int batch) { return qr_layout(m, k, batch).to
 // matrix; writes the reflectors (below the diagonal) and R (on and above it)
 // back into Xt, the reflectors as full rows into Vr (zeros above, 1 on the
 // diagonal) and the panel's T.  NT threads, RM rows per thread
-// (m - p0 <= NT RM), PWT columns.
+// (m - p0 <= NT RM), w <= PWT columns.
 //
 // One block-wide reduction per column: with v = [1; x_below scale] every dot
 // product the step needs follows from the raw sums s_l = sum_{i > c} x_ij x_il
@@ -83,13 +91,13 @@ size_t qr_work_bytes(int m, int k, int batch) { return qr_layout(m, k, batch).to
 // and s_j = |x_below|^2.  The sums go through LDS in two stages.
 template <int NT, int RM, int PWT>
 __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr_all, double* T_all,
-                                                      double* tau_all, int m, int k, long sX, long sT, int p0) {
+                                                      double* tau_all, int m, int k, long sX, long sT, int p0,
+                                                      int w) {
   constexpr int NSEG = NT / PWT;   // stage-2 segments of PWT partial rows each
   const int b = blockIdx.x;
   double* Xt = Xt_all + b * sX;
   double* Vr = Vr_all + b * sX;
   double* Tp = T_all + b * sT + (long)(p0 / TSLOT) * PW * PW;
-  const int w = min(PWT, k - p0);
   const int t = threadIdx.x;
   __shared__ double buf[NT][PWT + 1];
   __shared__ double seg[NSEG][PWT + 1];
@@ -105,7 +113,11 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
   }
   for (int e = t; e < PW * PW; e += NT) Ts[e / PW][e % PW] = 0.0;
   __syncthreads();
-  for (int j = 0; j < w; ++j) {
+  // columns of the panel, expanded at compile time so that every column index
+  // (and with it every register index) is a constant
+  auto column = [&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    if (j >= w) return;   // uniform
     const int c = p0 + j;
     double* rc = rowc[j & 1];
     // partial sums over this thread's rows below the diagonal; the owner of
@@ -116,10 +128,7 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
       const int i = p0 + t + NT * r;
-      double xj = 0.0;
-#pragma unroll
-      for (int l = 0; l < PWT; ++l)
-        if (l == j) xj = x[r][l];
+      const double xj = x[r][j];
       if (i > c && i < m) {
 #pragma unroll
         for (int l = 0; l < PWT; ++l) part[l] += xj * x[r][l];
@@ -153,33 +162,36 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
       tau = (beta - x0) / beta;
       scale = 1.0 / (x0 - beta);
     }
+    // coefficients of the update of columns l > j (and the T recurrence)
+    double d[PWT];
+#pragma unroll
+    for (int l = 0; l < PWT; ++l) d[l] = (l != j) ? rc[l] + scale * S[l] : 0.0;
     // v into column j (R entry on the diagonal), then H_j on columns l > j
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
       const int i = p0 + t + NT * r;
-      double vi = 0.0;
+      const bool below = i > c && i < m;
+      const double xs = x[r][j] * scale;
+      const double vi = (i == c) ? 1.0 : (below ? xs : 0.0);
+      x[r][j] = (i == c) ? beta : (below ? xs : x[r][j]);
+      const double tv = tau * vi;
 #pragma unroll
-      for (int l = 0; l < PWT; ++l)
-        if (l == j) {
-          if (i > c && i < m) x[r][l] *= scale;
-          if (i == c) x[r][l] = beta;
-          vi = (i == c) ? 1.0 : ((i > c && i < m) ? x[r][l] : 0.0);
-        }
-#pragma unroll
-      for (int l = 0; l < PWT; ++l)
-        if (l > j) x[r][l] -= tau * (rc[l] + scale * S[l]) * vi;
+      for (int l = j + 1; l < PWT; ++l) x[r][l] -= tv * d[l];
     }
     // T column j:  T[0:j, j] = -tau T[0:j, 0:j] z,  z_q = v_q . v_j = d_q
     if (t < j) {
       double a = 0.0;
-      for (int q = t; q < j; ++q) a += Ts[t][q] * (rc[q] + scale * S[q]);
+#pragma unroll
+      for (int q = 0; q < j; ++q)
+        if (q >= t) a += Ts[t][q] * d[q];
       Ts[t][j] = -tau * a;
     }
     if (t == j) {
       Ts[j][j] = tau;
       tau_all[(long)b * k + c] = tau;
     }
-  }
+  };
+  static_for(column, std::make_integer_sequence<int, PWT>{});
   __syncthreads();
   // write back: Xt rows p0 .. p0 + w - 1, the reflector rows, T
 #pragma unroll
@@ -257,8 +269,30 @@ __global__ __launch_bounds__(256) void qr_rowprod_partial_kernel(const double* A
 // diagonal blocks: H_a H_c = I - [V_a V_c] [[T_aa, T_ac], [0, T_cc]] [V_a V_c]^T
 // with T_ac = -T_aa S_ac T_cc, from 1 x 1 blocks (T_ii = tau_i) up to nv.
 // T is written NBW x NBW (zero below the diagonal and beyond nv).
-__global__ __launch_bounds__(256) void qr_tblock_kernel(const double* P_all, int nch, int nv, const double* tau_all,
-                                                        long sTau, double* TB_all, long sTB) {
+// Sum over the chunk partials (in chunk order, eight chunks' loads in
+// flight) of E entries per thread of the 64 x 64 tiles, entry e = tid + NTH i.
+template <int NTH, int E, typename Pred>
+__device__ __forceinline__ void sum_partials(const double* P, int nch, int tid, Pred need, double (&acc)[E]) {
+#pragma unroll
+  for (int i = 0; i < E; ++i) acc[i] = 0.0;
+  for (int ch0 = 0; ch0 < nch; ch0 += 8) {
+    double v[8][E];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int e = tid + NTH * i;
+        v[q][i] = (ch0 + q < nch && need(e)) ? P[(long)(ch0 + q) * NBW * NBW + e] : 0.0;
+      }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int i = 0; i < E; ++i) acc[i] += v[q][i];
+  }
+}
+
+__global__ __launch_bounds__(1024) void qr_tblock_kernel(const double* P_all, int nch, int nv, const double* tau_all,
+                                                         long sTau, double* TB_all, long sTB) {
   const int b = blockIdx.x;
   const double* P = P_all + (long)b * nch * NBW * NBW;
   const double* tau = tau_all + b * sTau;
@@ -267,25 +301,32 @@ __global__ __launch_bounds__(256) void qr_tblock_kernel(const double* P_all, int
   __shared__ double Tm[NBW][NBW + 1];
   __shared__ double X[NBW][NBW + 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < NBW * NBW; e += 256) {
-    const int r = e / NBW, c = e % NBW;
-    double a = 0.0;
-    if (r / 16 <= c / 16 && r < nv && c < nv)
-      for (int ch = 0; ch < nch; ++ch) a += P[(long)ch * NBW * NBW + e];
-    Ss[r][c] = a;
-    Tm[r][c] = (r == c && r < nv) ? tau[r] : 0.0;
+  {
+    double acc[4];
+    sum_partials<1024, 4>(P, nch, tid,
+                          [&](int e) {
+                            const int r = e / NBW, c = e % NBW;
+                            return r / 16 <= c / 16 && r < nv && c < nv;
+                          },
+                          acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 1024 * i, r = e / NBW, c = e % NBW;
+      Ss[r][c] = acc[i];
+      Tm[r][c] = (r == c && r < nv) ? tau[r] : 0.0;
+    }
   }
   __syncthreads();
   for (int h = 1; h < NBW; h *= 2) {
     const int nent = (NBW / (2 * h)) * h * h;
-    for (int e = tid; e < nent; e += 256) {
+    for (int e = tid; e < nent; e += 1024) {
       const int s0 = 2 * h * (e / (h * h)), ii = (e / h) % h, jj = e % h;
       double a = 0.0;
       for (int q = 0; q <= jj; ++q) a += Ss[s0 + ii][s0 + h + q] * Tm[s0 + h + q][s0 + h + jj];
       X[s0 + ii][s0 + h + jj] = a;
     }
     __syncthreads();
-    for (int e = tid; e < nent; e += 256) {
+    for (int e = tid; e < nent; e += 1024) {
       const int s0 = 2 * h * (e / (h * h)), ii = (e / h) % h, jj = e % h;
       double a = 0.0;
       for (int q = ii; q < h; ++q) a += Tm[s0 + ii][s0 + q] * X[s0 + q][s0 + h + jj];
@@ -293,7 +334,7 @@ __global__ __launch_bounds__(256) void qr_tblock_kernel(const double* P_all, int
     }
     __syncthreads();
   }
-  for (int e = tid; e < NBW * NBW; e += 256) TB[e] = Tm[e / NBW][e % NBW];
+  for (int e = tid; e < NBW * NBW; e += 1024) TB[e] = Tm[e / NBW][e % NBW];
 }
 
 // In-block update: Y <- Y - (W T) V for the nt <= 64 rows of Y (length len,
@@ -313,12 +354,29 @@ __global__ __launch_bounds__(256) void qr_inblock_apply_kernel(double* Y_all, lo
   __shared__ double Wm[NBW][PW + 1];
   __shared__ double W2[NBW][PW + 1];
   __shared__ double Ts[PW][PW + 1];
-  for (int e = tid; e < NBW * PW; e += 256) {
-    const int r = e / PW, c = e % PW;
-    double a = 0.0;
-    if (r < nt && c < pw)
-      for (int ch = 0; ch < nch; ++ch) a += P[(long)ch * NBW * NBW + r * NBW + c];
-    Wm[r][c] = a;
+  {
+    double acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = 0.0;
+    for (int ch0 = 0; ch0 < nch; ch0 += 8) {
+      double v[8][4];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = tid + 256 * i, r = e / PW, c = e % PW;
+          v[q][i] = (ch0 + q < nch && r < nt && c < pw) ? P[(long)(ch0 + q) * NBW * NBW + r * NBW + c] : 0.0;
+        }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += v[q][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 256 * i;
+      Wm[e / PW][e % PW] = acc[i];
+    }
   }
   for (int e = tid; e < PW * PW; e += 256) Ts[e / PW][e % PW] = T[e];
   __syncthreads();
@@ -417,18 +475,18 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
       const dim3 g(batch);
       if (P.nt_threads == 256) {
         if (P.rm == 1)
-          hipLaunchKernelGGL((qr_panel_kernel<256, 1, 16>), g, dim3(256), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+          hipLaunchKernelGGL((qr_panel_kernel<256, 1, 16>), g, dim3(256), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
         else if (P.rm == 2)
-          hipLaunchKernelGGL((qr_panel_kernel<256, 2, 16>), g, dim3(256), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+          hipLaunchKernelGGL((qr_panel_kernel<256, 2, 16>), g, dim3(256), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
         else
-          hipLaunchKernelGGL((qr_panel_kernel<256, 4, 16>), g, dim3(256), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+          hipLaunchKernelGGL((qr_panel_kernel<256, 4, 16>), g, dim3(256), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
       } else if (P.nt_threads == 512) {
-        hipLaunchKernelGGL((qr_panel_kernel<512, 4, 16>), g, dim3(512), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+        hipLaunchKernelGGL((qr_panel_kernel<512, 4, 16>), g, dim3(512), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
       } else {
         if (P.rm <= 3)
-          hipLaunchKernelGGL((qr_panel_kernel<1024, 3, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+          hipLaunchKernelGGL((qr_panel_kernel<1024, 3, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
         else
-          hipLaunchKernelGGL((qr_panel_kernel<1024, 4, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0);
+          hipLaunchKernelGGL((qr_panel_kernel<1024, 4, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
       }
       e = hipGetLastError();
       const int nt = j1 - p0 - pw;   // rest of the outer block (rows of Xt)
@@ -456,7 +514,7 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
     e = hipGetLastError();
     if (e != hipSuccess) break;
     double* TBb = TB + (long)bi * NBW * NBW;
-    hipLaunchKernelGGL(qr_tblock_kernel, dim3(batch), dim3(256), 0, s, (const double*)Pb, nch, nv,
+    hipLaunchKernelGGL(qr_tblock_kernel, dim3(batch), dim3(1024), 0, s, (const double*)Pb, nch, nv,
                        (const double*)(tau + j0), L.sTau, TBb, L.sTB);
     e = hipGetLastError();
     if (nt <= 0 || e != hipSuccess) continue;

@@ -143,24 +143,34 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(const double* Gt_all, 
   const int pr = blockIdx.x, ch = blockIdx.y;
   int p, q;
   circle_pair(nb, round, pr, p, q);
-  __shared__ double sm[4 * 1024];          // staging [4][32][17], then the wave partials [4][1024]
+  __shared__ double sm[4 * 4 * JP * 17];   // staging [wave][sub][32][17], then the wave partials [4][1024]
   __shared__ int rowidx[JP];
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
   if (tid < JP) rowidx[tid] = (tid < JW) ? p * JW + tid : q * JW + (tid - JW);
   __syncthreads();
-  double* buf = sm + wv * (JP * 17);
   d4v acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0, 0, 0, 0};
   const int c0 = ch * JCH + wv * 64;
-  for (int sub = 0; sub < 4; ++sub) {      // 16 entries at a time, uniform for every wave
-    const int cs = c0 + sub * 16;
+  {
+    // all 4 x 16 entries of the wave's 64-entry slice in flight at once
+    double v[4][8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int r = i * 4 + (l >> 4), c = l & 15;
-      buf[r * 17 + c] = (cs + c < m) ? Gt[(long)rowidx[r] * m + cs + c] : 0.0;
-    }
-    __syncthreads();
+    for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = i * 4 + (l >> 4), c = c0 + sub * 16 + (l & 15);
+        v[sub][i] = (c < m) ? Gt[(long)rowidx[r] * m + c] : 0.0;
+      }
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sm[((wv * 4 + sub) * JP + i * 4 + (l >> 4)) * 17 + (l & 15)] = v[sub][i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int sub = 0; sub < 4; ++sub) {
+    const double* buf = sm + (wv * 4 + sub) * JP * 17;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int kc = kk * 4 + (l >> 4);
@@ -170,8 +180,8 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(const double* Gt_all, 
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc[1][1], 0, 0, 0);
     }
-    __syncthreads();
   }
+  __syncthreads();
   // wave partials in the fragment order e = ((ti*2 + tj)*4 + r)*64 + lane
   for (int ti = 0; ti < 2; ++ti)
     for (int tj = 0; tj < 2; ++tj)
@@ -225,16 +235,34 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
   }
   double* offv = off_all + b * sOff;
   const double negl2 = 1e-26 * fro2_all[b];   // f^2 = (1e-13 |M|_F)^2
-  __shared__ double H[JP][JP + 1];
+  __shared__ double H2[2][JP][JP + 1];
   __shared__ double W[JP][JP + 1];
   __shared__ double wmax[4];
+  double (*H)[JP + 1] = H2[0];
   __shared__ int any;
   const double* part = part_all + ((long)b * pairs + pr) * nchunk * 1024;
-  for (int e = tid; e < 1024; e += 256) {
-    double a = 0.0;
-    for (int c = 0; c < nchunk; ++c) a += part[(long)c * 1024 + e];
-    const int lane = e & 63, r = (e >> 6) & 3, tt = e >> 8, ti = tt >> 1, tj = tt & 1;
-    H[ti * 16 + 4 * r + (lane >> 4)][tj * 16 + (lane & 15)] = a;
+  {
+    // entries e = tid + 256 i, summed over the chunks in order with four
+    // chunks' loads in flight
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < nchunk; c0 += 4) {
+      double v[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[q][i] = (c0 + q < nchunk) ? part[(long)(c0 + q) * 1024 + tid + 256 * i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (c0 + q < nchunk) acc[i] += v[q][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 256 * i;
+      const int lane = e & 63, r = (e >> 6) & 3, tt = e >> 8, ti = tt >> 1, tj = tt & 1;
+      H[ti * 16 + 4 * r + (lane >> 4)][tj * 16 + (lane & 15)] = acc[i];
+    }
   }
   for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = (e / JP == e % JP) ? 1.0 : 0.0;
   __syncthreads();
@@ -267,32 +295,38 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
   }
   if (!(om > tol)) return;   // converged pair (or NaN: leave the data as is)
 
+  // H is double-buffered: round rr reads one copy and writes the other (the
+  // 2 x 2 blocks of all threads cover H), so one barrier per round suffices;
+  // W entries are read and written by their owner only within a round.
   const double thr = 0.1 * tol;
   const int pp = tid >> 4, qq = tid & 15;
+  int cur = 0;
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     if (tid == 0) any = 0;
     __syncthreads();
     for (int rr = 0; rr < JP - 1; ++rr) {
+      double (*Hc)[JP + 1] = H2[cur];
+      double (*Hn)[JP + 1] = H2[cur ^ 1];
       int ap, cp, aq, cq;
       circle_pair(JP, rr, pp, ap, cp);
       circle_pair(JP, rr, qq, aq, cq);
       double c1, s1, c2, s2;
-      jacobi_rot(H[ap][ap], H[cp][cp], H[ap][cp], thr, negl2, c1, s1);
-      jacobi_rot(H[aq][aq], H[cq][cq], H[aq][cq], thr, negl2, c2, s2);
+      jacobi_rot(Hc[ap][ap], Hc[cp][cp], Hc[ap][cp], thr, negl2, c1, s1);
+      jacobi_rot(Hc[aq][aq], Hc[cq][cq], Hc[aq][cq], thr, negl2, c2, s2);
       if (qq == 0 && s1 != 0.0) any = 1;
-      const double h00 = H[ap][aq], h01 = H[ap][cq], h10 = H[cp][aq], h11 = H[cp][cq];
+      const double h00 = Hc[ap][aq], h01 = Hc[ap][cq], h10 = Hc[cp][aq], h11 = Hc[cp][cq];
       const double w00 = W[ap][aq], w01 = W[ap][cq], w10 = W[cp][aq], w11 = W[cp][cq];
       const double r00 = c1 * h00 - s1 * h10, r01 = c1 * h01 - s1 * h11;
       const double r10 = s1 * h00 + c1 * h10, r11 = s1 * h01 + c1 * h11;
-      __syncthreads();
-      H[ap][aq] = c2 * r00 - s2 * r01;
-      H[ap][cq] = s2 * r00 + c2 * r01;
-      H[cp][aq] = c2 * r10 - s2 * r11;
-      H[cp][cq] = s2 * r10 + c2 * r11;
+      Hn[ap][aq] = c2 * r00 - s2 * r01;
+      Hn[ap][cq] = s2 * r00 + c2 * r01;
+      Hn[cp][aq] = c2 * r10 - s2 * r11;
+      Hn[cp][cq] = s2 * r10 + c2 * r11;
       W[ap][aq] = c2 * w00 - s2 * w01;
       W[ap][cq] = s2 * w00 + c2 * w01;
       W[cp][aq] = c2 * w10 - s2 * w11;
       W[cp][cq] = s2 * w10 + c2 * w11;
+      cur ^= 1;
       __syncthreads();
     }
     if (!any) break;
@@ -329,12 +363,18 @@ __global__ __launch_bounds__(256) void jacobi_rotate_kernel(double* Gt_all, doub
     const int cb = (isG ? blockIdx.y : blockIdx.y - nchG) * JCH;
     atomicAdd(entries, (unsigned long long)min(JCH, len - cb));
   }
+  // the wave's 64 entries of all 32 columns are loaded before any is written
+  double old[4][8];
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc) {
+    const int c = c0 + tc * 16 + (l & 15);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) old[tc][kk] = (c < len) ? X[(long)rowidx[kk * 4 + (l >> 4)] * len + c] : 0.0;
+  }
+#pragma unroll
   for (int tc = 0; tc < 4; ++tc) {
     const int c = c0 + tc * 16 + (l & 15);
     const bool in = c < len;
-    double old[8];
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) old[kk] = in ? X[(long)rowidx[kk * 4 + (l >> 4)] * len + c] : 0.0;
     d4v d[2];
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti) {
@@ -342,7 +382,7 @@ __global__ __launch_bounds__(256) void jacobi_rotate_kernel(double* Gt_all, doub
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
         const double a = Ws[kk * 4 + (l >> 4)][ti * 16 + (l & 15)];   // (W^T)[i][j]
-        d[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, old[kk], d[ti], 0, 0, 0);
+        d[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, old[tc][kk], d[ti], 0, 0, 0);
       }
     }
     if (in) {
