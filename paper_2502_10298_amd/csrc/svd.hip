@@ -195,22 +195,29 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(const double* Gt_all, 
 // new row a = c row_a - s row_c, new row c = s row_a + c row_c (same on
 // columns).  Below the threshold the identity is returned.  With D = h_cc -
 // h_aa and E = 2 h_ac the tangent of the smaller angle is
-// t = sign(D E) |E| / (|D| + sqrt(D^2 + E^2)), and c = 1 / sqrt(1 + t^2) comes
-// from the hardware reciprocal square root refined by two Newton steps
-// (c^2 + s^2 = 1 to working accuracy, which keeps W orthogonal).
+// t = sign(D E) |E| / (|D| + sqrt(D^2 + E^2)).  The square root and the
+// quotient come from the hardware reciprocal square root and reciprocal,
+// each refined by a Newton step (t need not be exact: any t gives an exact
+// rotation), and c = 1 / sqrt(1 + t^2) from the reciprocal square root
+// refined by two Newton steps (c^2 + s^2 = 1 to working accuracy, which keeps
+// W orthogonal).  Branch-free, so that the two rotations a thread needs per
+// round overlap.
 __device__ inline void jacobi_rot(double haa, double hcc, double hac, double thr, double negl2, double& c, double& s) {
-  c = 1.0;
-  s = 0.0;
-  if (hac * hac > thr * thr * fmax(haa, negl2) * fmax(hcc, negl2)) {
-    const double D = hcc - haa, E = 2.0 * hac;
-    const double t = ((D >= 0.0) == (E >= 0.0) ? 1.0 : -1.0) * fabs(E) / (fabs(D) + sqrt(D * D + E * E));
-    const double x = 1.0 + t * t;
-    double y = __builtin_amdgcn_rsq(x);
-    y = y * (1.5 - 0.5 * x * y * y);
-    y = y * (1.5 - 0.5 * x * y * y);
-    c = y;
-    s = y * t;
-  }
+  const bool active = hac * hac > thr * thr * fmax(haa, negl2) * fmax(hcc, negl2);
+  const double D = hcc - haa, E = 2.0 * hac;
+  const double q = D * D + E * E;
+  double y = __builtin_amdgcn_rsq(q);
+  y = y * (1.5 - 0.5 * q * y * y);
+  const double den = fabs(D) + q * y;   // |D| + sqrt(q)
+  double inv = __builtin_amdgcn_rcp(den);
+  inv = inv * (2.0 - den * inv);
+  const double t = ((D >= 0.0) == (E >= 0.0) ? 1.0 : -1.0) * fabs(E) * inv;
+  const double x = 1.0 + t * t;
+  double z = __builtin_amdgcn_rsq(x);
+  z = z * (1.5 - 0.5 * x * z * z);
+  z = z * (1.5 - 0.5 * x * z * z);
+  c = active ? z : 1.0;
+  s = active ? z * t : 0.0;
 }
 
 // One workgroup (four wavefronts) per block pair.  Sums the Gram partials,
