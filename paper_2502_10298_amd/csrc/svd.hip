@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(const double* Gt_all, 
   const int pr = blockIdx.x, ch = blockIdx.y;
   int p, q;
   circle_pair(nb, round, pr, p, q);
-  __shared__ double sm[4 * 4 * JP * 17];   // staging [wave][sub][32][17], then the wave partials [4][1024]
+  __shared__ double sm[4 * 2 * JP * 17];   // staging [wave][2 subs][32][17], then the wave partials [4][1024]
   __shared__ int rowidx[JP];
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
   if (tid < JP) rowidx[tid] = (tid < JW) ? p * JW + tid : q * JW + (tid - JW);
@@ -152,43 +152,46 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(const double* Gt_all, 
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0, 0, 0, 0};
   const int c0 = ch * JCH + wv * 64;
-  {
-    // all 4 x 16 entries of the wave's 64-entry slice in flight at once
-    double v[4][8];
+  // all 4 x 16 entries of the wave's 64-entry slice in flight at once; staged
+  // through LDS two 16-entry subs at a time
+  double v[4][8];
 #pragma unroll
-    for (int sub = 0; sub < 4; ++sub)
+  for (int sub = 0; sub < 4; ++sub)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int r = i * 4 + (l >> 4), c = c0 + sub * 16 + (l & 15);
-        v[sub][i] = (c < m) ? Gt[(long)rowidx[r] * m + c] : 0.0;
-      }
-#pragma unroll
-    for (int sub = 0; sub < 4; ++sub)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) sm[((wv * 4 + sub) * JP + i * 4 + (l >> 4)) * 17 + (l & 15)] = v[sub][i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int sub = 0; sub < 4; ++sub) {
-    const double* buf = sm + (wv * 4 + sub) * JP * 17;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int kc = kk * 4 + (l >> 4);
-      const double a0 = buf[(l & 15) * 17 + kc], a1 = buf[(16 + (l & 15)) * 17 + kc];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc[1][1], 0, 0, 0);
+    for (int i = 0; i < 8; ++i) {
+      const int r = i * 4 + (l >> 4), c = c0 + sub * 16 + (l & 15);
+      v[sub][i] = (c < m) ? Gt[(long)rowidx[r] * m + c] : 0.0;
     }
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sm[((wv * 2 + s2) * JP + i * 4 + (l >> 4)) * 17 + (l & 15)] = v[2 * half + s2][i];
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const double* buf = sm + (wv * 2 + s2) * JP * 17;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kc = kk * 4 + (l >> 4);
+        const double a0 = buf[(l & 15) * 17 + kc], a1 = buf[(16 + (l & 15)) * 17 + kc];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, acc[0][1], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc[1][1], 0, 0, 0);
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // wave partials in the fragment order e = ((ti*2 + tj)*4 + r)*64 + lane
+  // (the lower off-diagonal tile (1, 0) is the transpose of (0, 1) and is not formed)
   for (int ti = 0; ti < 2; ++ti)
     for (int tj = 0; tj < 2; ++tj)
-      for (int r = 0; r < 4; ++r) sm[wv * 1024 + ((ti * 2 + tj) * 4 + r) * 64 + l] = acc[ti][tj][r];
+      if (ti <= tj)
+        for (int r = 0; r < 4; ++r) sm[wv * 1024 + ((ti * 2 + tj) * 4 + r) * 64 + l] = acc[ti][tj][r];
   __syncthreads();
   double* out = part_all + (((long)b * pairs + pr) * nchunk + ch) * 1024;
-  for (int e = tid; e < 1024; e += 256) out[e] = (sm[e] + sm[1024 + e]) + (sm[2048 + e] + sm[3072 + e]);
+  for (int e = tid; e < 1024; e += 256)
+    if ((e >> 8) != 2) out[e] = (sm[e] + sm[1024 + e]) + (sm[2048 + e] + sm[3072 + e]);
 }
 
 // Jacobi rotation that zeroes the (a, c) entry of a symmetric 2 x 2 block:
@@ -227,10 +230,11 @@ __device__ inline void jacobi_rot(double haa, double hcc, double hac, double thr
 // and of W (the accumulated rotations) at row pair p and column pair q,
 // computes both rotations itself and forms J_p^T H J_q and W J_q in
 // registers: one barrier after all reads, one after all writes.
-__global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_all, int nchunk, int np, int round,
-                                                           double tol, double* off_all, long sOff, double* W_all,
-                                                           int* rot_all, const int* done, int inner_sweeps,
-                                                           const double* fro2_all) {
+__global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_all, int nchunk, int m, int np,
+                                                           int round, double tol, double* off_all, long sOff,
+                                                           double* W_all, int* rot_all, const int* done,
+                                                           int inner_sweeps, const double* fro2_all,
+                                                           unsigned long long* entries) {
   const int b = blockIdx.y;
   const int nb = np / JW, pairs = nb / 2;
   const int pr = blockIdx.x;
@@ -257,7 +261,8 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[q][i] = (c0 + q < nchunk) ? part[(long)(c0 + q) * 1024 + tid + 256 * i] : 0.0;
+        for (int i = 0; i < 4; ++i)
+          v[q][i] = (c0 + q < nchunk && i != 2) ? part[(long)(c0 + q) * 1024 + tid + 256 * i] : 0.0;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -266,10 +271,16 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+      if (i == 2) continue;   // tile (1, 0): the transpose of tile (0, 1), filled below
       const int e = tid + 256 * i;
       const int lane = e & 63, r = (e >> 6) & 3, tt = e >> 8, ti = tt >> 1, tj = tt & 1;
       H[ti * 16 + 4 * r + (lane >> 4)][tj * 16 + (lane & 15)] = acc[i];
     }
+  }
+  __syncthreads();
+  {
+    const int i = tid >> 4, j = tid & 15;
+    H[16 + j][i] = H[i][16 + j];
   }
   for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = (e / JP == e % JP) ? 1.0 : 0.0;
   __syncthreads();
@@ -299,6 +310,8 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
   if (tid == 0) {
     offv[(long)round * pairs + pr] = om;
     *rot = (om > tol) ? 1 : 0;
+    // column-length entries of G and V the rotation will touch (statistics)
+    if (om > tol) atomicAdd(entries, (unsigned long long)(m + np));
   }
   if (!(om > tol)) return;   // converged pair (or NaN: leave the data as is)
 
@@ -343,12 +356,15 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
   for (int e = tid; e < JP * JP; e += 256) Wout[e] = W[e / JP][e % JP];
 }
 
-// new columns = old columns W for the rows of Gt (chunks 0 .. nchG-1, length
-// m) and of Vt (chunks nchG .., length np); each wave owns 64 entries of the
-// column length and reads all 32 columns there before writing them back.
-__global__ __launch_bounds__(256) void jacobi_rotate_kernel(double* Gt_all, double* Vt_all, int m, int np, int round,
+// new columns = old columns W for the rows of Gt (chunks 0 .. nchG-1 of JCHR
+// entries, length m) and of Vt (chunks nchG .., length np); each of the eight
+// wavefronts owns 64 entries of the column length and reads all 32 columns
+// there before writing them back.
+static constexpr int JCHR = 512;
+
+__global__ __launch_bounds__(512) void jacobi_rotate_kernel(double* Gt_all, double* Vt_all, int m, int np, int round,
                                                             long sG, long sV, const double* W_all, const int* rot_all,
-                                                            int nchG, const int* done, unsigned long long* entries) {
+                                                            int nchG, const int* done) {
   const int b = blockIdx.z;
   const int nb = np / JW, pairs = nb / 2;
   const int pr = blockIdx.x;
@@ -359,17 +375,14 @@ __global__ __launch_bounds__(256) void jacobi_rotate_kernel(double* Gt_all, doub
   __shared__ int rowidx[JP];
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
   const double* Wg = W_all + ((long)b * pairs + pr) * JP * JP;
-  for (int e = tid; e < JP * JP; e += 256) Ws[e / JP][e % JP] = Wg[e];
+  for (int e = tid; e < JP * JP; e += 512) Ws[e / JP][e % JP] = Wg[e];
   if (tid < JP) rowidx[tid] = (tid < JW) ? p * JW + tid : q * JW + (tid - JW);
   __syncthreads();
   const bool isG = (int)blockIdx.y < nchG;
   double* X = isG ? Gt_all + b * sG : Vt_all + b * sV;
   const int len = isG ? m : np;
-  const int c0 = (isG ? blockIdx.y : blockIdx.y - nchG) * JCH + wv * 64;
-  if (tid == 0) {   // column-length entries rotated by this workgroup (statistics)
-    const int cb = (isG ? blockIdx.y : blockIdx.y - nchG) * JCH;
-    atomicAdd(entries, (unsigned long long)min(JCH, len - cb));
-  }
+  const int c0 = (isG ? blockIdx.y : blockIdx.y - nchG) * JCHR + wv * 64;
+  if (c0 >= len) return;   // whole wave past the end (no barrier follows)
   // the wave's 64 entries of all 32 columns are loaded before any is written
   double old[4][8];
 #pragma unroll
@@ -378,25 +391,29 @@ __global__ __launch_bounds__(256) void jacobi_rotate_kernel(double* Gt_all, doub
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) old[tc][kk] = (c < len) ? X[(long)rowidx[kk * 4 + (l >> 4)] * len + c] : 0.0;
   }
+  // eight independent accumulator chains (4 column tiles x 2 row tiles), interleaved
+  d4v d[4][2];
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc)
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti) d[tc][ti] = d4v{0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    const double a0 = Ws[kk * 4 + (l >> 4)][l & 15], a1 = Ws[kk * 4 + (l >> 4)][16 + (l & 15)];   // (W^T)[i][j]
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc) {
+      d[tc][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, old[tc][kk], d[tc][0], 0, 0, 0);
+      d[tc][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, old[tc][kk], d[tc][1], 0, 0, 0);
+    }
+  }
 #pragma unroll
   for (int tc = 0; tc < 4; ++tc) {
     const int c = c0 + tc * 16 + (l & 15);
-    const bool in = c < len;
-    d4v d[2];
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti) {
-      d[ti] = d4v{0, 0, 0, 0};
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const double a = Ws[kk * 4 + (l >> 4)][ti * 16 + (l & 15)];   // (W^T)[i][j]
-        d[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, old[tc][kk], d[ti], 0, 0, 0);
-      }
-    }
-    if (in) {
+    if (c < len) {
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) X[(long)rowidx[ti * 16 + 4 * r + (l >> 4)] * len + c] = d[ti][r];
+        for (int r = 0; r < 4; ++r) X[(long)rowidx[ti * 16 + 4 * r + (l >> 4)] * len + c] = d[tc][ti][r];
     }
   }
 }
@@ -475,15 +492,21 @@ __global__ void svd_permute_rows_kernel(const double* Xin_all, double* Xout_all,
   for (int i = threadIdx.x; i < len; i += blockDim.x) out[i] = src[i];
 }
 
+// position of column j in the descending-norm order (ties: lower index
+// first); the norms of the batch entry are staged in LDS (n <= 4096)
 __global__ void svd_rank_kernel(const double* norms_all, int n, int np, int* rank_all) {
   const int b = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
   const double* s = norms_all + (long)b * np;
-  double sj = s[j];
+  __shared__ double sn[4096];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sn[i] = s[i];
+  __syncthreads();
+  if (j >= n) return;
+  const double sj = sn[j];
   int r = 0;
+#pragma unroll 8
   for (int i = 0; i < n; ++i) {
-    double si = s[i];
+    const double si = sn[i];
     r += (si > sj || (si == sj && i < j)) ? 1 : 0;
   }
   rank_all[(long)b * np + j] = r;
@@ -550,6 +573,7 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
   }();
   err = hipSuccess;
   int running = batch;
+  const int nrG = (n + JCHR - 1) / JCHR, nrV = (L.np + JCHR - 1) / JCHR;   // rotation chunks
   for (int sw = 0; sw < max_sweeps; ++sw) {
     // columns in descending norm order before every sweep (the large ones
     // meet first in the tournament, which cuts the sweep count of graded
@@ -572,11 +596,10 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
       launch_timed(KC_JACOBI_GRAM, gram_fl, gram_by, jacobi_gram_kernel, dim3(L.pairs, L.nchG, batch), dim3(256), 0,
                    s, (const double*)Gt, n, L.np, r, L.sG, part, L.nchG, (const int*)done);
       launch_timed(KC_JACOBI_SOLVE, 0.0, solve_by, jacobi_solve_kernel, dim3(L.pairs, batch), dim3(256), 0, s,
-                   (const double*)part, L.nchG, L.np, r, tol, off, L.sOff, Wr, rot, (const int*)done, inner,
-                   (const double*)fro2);
-      launch_timed(KC_JACOBI_ROTATE, 0.0, 0.0, jacobi_rotate_kernel, dim3(L.pairs, L.nchG + L.nchV, batch), dim3(256),
-                   0, s, Gt, Vt, n, L.np, r, L.sG, L.sV, (const double*)Wr, (const int*)rot, L.nchG,
-                   (const int*)done, cnt);
+                   (const double*)part, L.nchG, n, L.np, r, tol, off, L.sOff, Wr, rot, (const int*)done, inner,
+                   (const double*)fro2, cnt);
+      launch_timed(KC_JACOBI_ROTATE, 0.0, 0.0, jacobi_rotate_kernel, dim3(L.pairs, nrG + nrV, batch), dim3(512), 0, s,
+                   Gt, Vt, n, L.np, r, L.sG, L.sV, (const double*)Wr, (const int*)rot, nrG, (const int*)done);
     }
     hipLaunchKernelGGL(svd_check_kernel, dim3(batch), dim3(256), 0, s, off, L.sOff, tol, done);
     ++sweeps;
@@ -615,25 +638,45 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
 // half the sweeps; the QR costs less than one sweep.
 
 // column norms of row-major n x n matrices (thread = column, coalesced rows)
-__global__ void pre_colnorm_kernel(const double* A_all, int n, double* nrm_all) {
+__global__ __launch_bounds__(256) void pre_colnorm_kernel(const double* A_all, int n, double* nrm_all) {
   const int b = blockIdx.y;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+  const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;   // 64 columns x 4 row groups
+  const int c = blockIdx.x * 64 + cl;
   const double* A = A_all + (long)b * n * n;
-  double acc = 0.0;
-  for (int r = 0; r < n; ++r) acc += A[(long)r * n + c] * A[(long)r * n + c];
-  nrm_all[(long)b * n + c] = acc;
+  __shared__ double red[4][64];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c < n) {
+    int r = rg;
+    for (; r + 12 < n; r += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double v = A[(long)(r + 4 * u) * n + c];
+        acc[u] += v * v;
+      }
+    }
+    for (; r < n; r += 4) {
+      const double v = A[(long)r * n + c];
+      acc[0] += v * v;
+    }
+  }
+  red[rg][cl] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (rg == 0 && c < n) nrm_all[(long)b * n + c] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
 }
 
 // position of column c in the decreasing-norm order (ties: lower index first)
 __global__ void pre_rank_kernel(const double* nrm_all, int n, int* rank_all) {
   const int b = blockIdx.y;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
   const double* s = nrm_all + (long)b * n;
-  const double sc = s[c];
+  __shared__ double sn[4096];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sn[i] = s[i];
+  __syncthreads();
+  if (c >= n) return;
+  const double sc = sn[c];
   int r = 0;
-  for (int i = 0; i < n; ++i) r += (s[i] > sc || (s[i] == sc && i < c)) ? 1 : 0;
+#pragma unroll 8
+  for (int i = 0; i < n; ++i) r += (sn[i] > sc || (sn[i] == sc && i < c)) ? 1 : 0;
   rank_all[(long)b * n + c] = r;
 }
 
@@ -729,7 +772,7 @@ hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, dou
   double* nrm = (double*)(w + L.offN);
   int* rk = (int*)(w + L.offRk);
   const long nn = (long)n * n;
-  hipLaunchKernelGGL(pre_colnorm_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, A, n, nrm);
+  hipLaunchKernelGGL(pre_colnorm_kernel, dim3((n + 63) / 64, batch), dim3(256), 0, s, A, n, nrm);
   hipLaunchKernelGGL(pre_rank_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, (const double*)nrm, n, rk);
   hipLaunchKernelGGL(pre_gather_kernel, dim3((n + 31) / 32, (n + 31) / 32, batch), dim3(256), 0, s, A,
                      (const int*)rk, n, Xt);
