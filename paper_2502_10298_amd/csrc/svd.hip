@@ -285,13 +285,14 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
   for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = (e / JP == e % JP) ? 1.0 : 0.0;
   __syncthreads();
 
-  // ---- convergence measure of this pair (NaN-propagating max) ----
+  // ---- convergence measure of this pair (NaN-propagating max); the
+  // hardware reciprocal square root is ample for a threshold test ----
   double om = 0.0;
   for (int e = tid; e < JP * JP; e += 256) {
     const int i = e / JP, j = e % JP;
     if (j > i) {
       const double hii = fmax(H[i][i], negl2), hjj = fmax(H[j][j], negl2);
-      double v = fabs(H[i][j]) / (sqrt(hii) * sqrt(hjj) + 1e-300);
+      double v = fabs(H[i][j]) * __builtin_amdgcn_rsq(hii * hjj);
       if (H[i][j] != H[i][j] || H[i][i] != H[i][i] || H[j][j] != H[j][j]) v = NAN;
       om = (v != v || om != om) ? NAN : fmax(om, v);
     }
@@ -318,22 +319,26 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
   // H is double-buffered: round rr reads one copy and writes the other (the
   // 2 x 2 blocks of all threads cover H), so one barrier per round suffices;
   // W entries are read and written by their owner only within a round.
+  // Thread (pp, qq) computes the rotation of index pair qq and takes that of
+  // pair pp from the lane of its wavefront that computed it.  The pairs of
+  // the circle tournament advance by one position per round.
   const double thr = 0.1 * tol;
   const int pp = tid >> 4, qq = tid & 15;
+  const int src = (l & 48) | pp;   // lane (pp mod 4, pp) of this wavefront
   int cur = 0;
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     if (tid == 0) any = 0;
     __syncthreads();
+    int ap, cp, aq, cq;
+    circle_pair(JP, 0, pp, ap, cp);
+    circle_pair(JP, 0, qq, aq, cq);
     for (int rr = 0; rr < JP - 1; ++rr) {
       double (*Hc)[JP + 1] = H2[cur];
       double (*Hn)[JP + 1] = H2[cur ^ 1];
-      int ap, cp, aq, cq;
-      circle_pair(JP, rr, pp, ap, cp);
-      circle_pair(JP, rr, qq, aq, cq);
-      double c1, s1, c2, s2;
-      jacobi_rot(Hc[ap][ap], Hc[cp][cp], Hc[ap][cp], thr, negl2, c1, s1);
+      double c2, s2;
       jacobi_rot(Hc[aq][aq], Hc[cq][cq], Hc[aq][cq], thr, negl2, c2, s2);
-      if (qq == 0 && s1 != 0.0) any = 1;
+      const double c1 = __shfl(c2, src), s1 = __shfl(s2, src);
+      if (s2 != 0.0) any = 1;
       const double h00 = Hc[ap][aq], h01 = Hc[ap][cq], h10 = Hc[cp][aq], h11 = Hc[cp][cq];
       const double w00 = W[ap][aq], w01 = W[ap][cq], w10 = W[cp][aq], w11 = W[cp][cq];
       const double r00 = c1 * h00 - s1 * h10, r01 = c1 * h01 - s1 * h11;
@@ -347,6 +352,17 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
       W[cp][aq] = c2 * w10 - s2 * w11;
       W[cp][cq] = s2 * w10 + c2 * w11;
       cur ^= 1;
+      // next round of the circle: index 0 keeps player 0, the others move on
+      if (pp == 0) ++cp;
+      else {
+        ap = (ap == JP - 1) ? 1 : ap + 1;
+        cp = (cp == JP - 1) ? 1 : cp + 1;
+      }
+      if (qq == 0) ++cq;
+      else {
+        aq = (aq == JP - 1) ? 1 : aq + 1;
+        cq = (cq == JP - 1) ? 1 : cq + 1;
+      }
       __syncthreads();
     }
     if (!any) break;
