@@ -80,14 +80,18 @@ template <typename T, typename V4, bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
                                                    const T* __restrict__ A, long lda, long sA,
                                                    const T* __restrict__ B, long ldb, long sB, T beta,
-                                                   T* __restrict__ C, long ldc, long sC) {
+                                                   T* __restrict__ C, long ldc, long sC, int zdiv, long sA2,
+                                                   long sB2, long sC2, int Ktot) {
   constexpr int BK = 32;
   __shared__ T As[BK][BM + 4];
   __shared__ T Bs[BK][BN + 4];
-  const long bz = blockIdx.z;
-  A += bz * sA;
-  B += bz * sB;
-  C += bz * sC;
+  // grid z = batch entry x K slice (zdiv slices of length K, the last one
+  // ending at Ktot; zdiv = 1: plain batched product)
+  const long bz = blockIdx.z / zdiv, sl = blockIdx.z % zdiv;
+  A += bz * sA + sl * sA2;
+  B += bz * sB + sl * sB2;
+  C += bz * sC + sl * sC2;
+  if (zdiv > 1) K = min(K, Ktot - (int)sl * K);
   const int bm = blockIdx.y * BM, bn = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -275,13 +279,39 @@ hipError_t gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double
   const double fl = 2.0 * M * N * (double)K * batch;
   const double by = 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1));
   if (!tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else if (tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else if (!tA && tB)
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
+  return hipGetLastError();
+}
+
+hipError_t gemm_f64_slices(hipStream_t s, bool tA, bool tB, int M, int N, int K, const double* A, long lda, long sA,
+                           const double* B, long ldb, long sB, double* P, int S, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0 || S < 1) return hipSuccess;
+  const int Ks = (K + S - 1) / S;
+  if ((long)(S - 1) * Ks >= K) return hipErrorInvalidValue;   // every slice non-empty
+  dim3 g = gemm_grid(M, N, batch * S);
+  const int kind = KC_GEMM_F64;
+  const double fl = 2.0 * M * N * (double)K * batch;
+  const double by = 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N * S);
+  const long sA2 = tA ? (long)Ks * lda : Ks, sB2 = tB ? (long)Ks : (long)Ks * ldb;
+  const long sP = (long)S * M * N, sP2 = (long)M * N;
+  if (!tA && !tB)
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, false>, g, dim3(256), 0, s, M, N, Ks, 1.0, A, lda, sA, B,
+                 ldb, sB, 0.0, P, (long)N, sP, S, sA2, sB2, sP2, K);
+  else if (tA && !tB)
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, false>, g, dim3(256), 0, s, M, N, Ks, 1.0, A, lda, sA, B,
+                 ldb, sB, 0.0, P, (long)N, sP, S, sA2, sB2, sP2, K);
+  else if (!tA && tB)
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, true>, g, dim3(256), 0, s, M, N, Ks, 1.0, A, lda, sA, B,
+                 ldb, sB, 0.0, P, (long)N, sP, S, sA2, sB2, sP2, K);
+  else
+    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, true>, g, dim3(256), 0, s, M, N, Ks, 1.0, A, lda, sA, B,
+                 ldb, sB, 0.0, P, (long)N, sP, S, sA2, sB2, sP2, K);
   return hipGetLastError();
 }
 
@@ -315,13 +345,13 @@ hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, in
     return hipGetLastError();
   }
   if (!tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<float, f4, false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<float, f4, false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else if (tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<float, f4, true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<float, f4, true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else if (!tA && tB)
-    launch_timed(kind, fl, by, gemm_kernel<float, f4, false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<float, f4, false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else
-    launch_timed(kind, fl, by, gemm_kernel<float, f4, true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    launch_timed(kind, fl, by, gemm_kernel<float, f4, true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   return hipGetLastError();
 }
 

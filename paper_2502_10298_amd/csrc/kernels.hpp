@@ -17,6 +17,11 @@ hipError_t gemm_f64(hipStream_t s, bool transA, bool transB, int M, int N, int K
                     double alpha, const double* A, long lda, long sA,
                     const double* B, long ldb, long sB, double beta,
                     double* C, long ldc, long sC, int batch);
+// K-sliced batched FP64 product: P[b][sl] = op(A_b) op(B_b) over the sl-th of
+// S slices of length ceil(K / S) (every slice non-empty), P[b][sl] row-major
+// M x N at stride M N, entry b at stride S M N.  The caller sums the slices.
+hipError_t gemm_f64_slices(hipStream_t s, bool transA, bool transB, int M, int N, int K, const double* A, long lda,
+                           long sA, const double* B, long ldb, long sB, double* P, int S, int batch);
 hipError_t gemm_f32(hipStream_t s, Prec mode, bool transA, bool transB, int M, int N, int K,
                     float alpha, const float* A, long lda, long sA,
                     const float* B, long ldb, long sB, float beta,

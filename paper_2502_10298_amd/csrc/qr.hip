@@ -15,9 +15,9 @@
 //   in-block: the rest of the outer block <- H^T (rest), one fused kernel;
 //   block:    the block's T (64 x 64) from S = V^T V and the taus
 //             (T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] S[0:i, i]), and
-//             the columns beyond the block <- H^T (columns) in two
-//             full-chip kernels on the matrix cores: W = Xt_trail V, then
-//             Xt_trail <- Xt_trail - (W T) V^T;
+//             the columns beyond the block <- H^T (columns) on the matrix
+//             cores: W = Xt_trail V in K slices, W T from the summed slices,
+//             then Xt_trail <- Xt_trail - (W T) V^T;
 //   Q:        Q = H_1 ... H_k [I; 0], accumulated backwards over the outer
 //             blocks with T^T, by the same two kernels.
 // Householder QR is backward stable: Q is orthonormal to working accuracy
@@ -35,6 +35,7 @@ namespace sctm {
 static constexpr int PW = 16;     // widest panel (T blocks are PW x PW)
 static constexpr int TSLOT = 4;   // narrowest panel: one T block per TSLOT columns
 static constexpr int NBW = 64;    // columns per outer block
+static constexpr int QR_SMAX = 4;  // K slices of the W = Y V^T products at most
 
 // f(integral_constant<int, J>) for J = Js... in order
 template <typename F, int... Js>
@@ -68,7 +69,7 @@ static QrLayout qr_layout(int m, int k, int batch) {
   L.offV = take(sizeof(double) * L.sX * batch);                // reflectors as rows [k][m]
   L.offT = take(sizeof(double) * L.sT * batch);                // T of every panel
   L.offTB = take(sizeof(double) * L.sTB * batch);              // T of every outer block
-  L.offW = take(sizeof(double) * L.sW * batch);                // W = Y V of a block update
+  L.offW = take(sizeof(double) * L.sW * QR_SMAX * batch);      // K slices of W = Y V^T of a block update
   L.offW2 = take(sizeof(double) * L.sW * batch);               // W T
   L.offP = take(sizeof(double) * L.sP * batch);                // chunk partials of S or of an in-block W
   L.offTau = take(sizeof(double) * L.sTau * batch);            // tau of every reflector
@@ -400,6 +401,41 @@ __global__ __launch_bounds__(256) void qr_inblock_apply_kernel(double* Y_all, lo
   }
 }
 
+// W2 = (sum of the S K-slices of W = Y V^T) T' for 16 rows of W per
+// workgroup (slices summed in order), T' = T (factorisation) or T^T (Q).
+// The slices come from gemm_f64_slices: nt x nv each, slice stride nt nv,
+// batch entry stride S nt nv.  W2 is written nt x nv, leading dimension NBW.
+template <bool TRANS_T>
+__global__ __launch_bounds__(256) void qr_w2_kernel(const double* P_all, int S, int nt, int nv,
+                                                    const double* TB_all, long sTB, double* W2_all, long sW2) {
+  const int b = blockIdx.y;
+  const long snn = (long)nt * nv;
+  const double* P = P_all + (long)b * S * snn;
+  const double* TB = TB_all + b * sTB;
+  double* W2 = W2_all + b * sW2;
+  const int tid = threadIdx.x, row0 = blockIdx.x * 16;
+  __shared__ double Ts[NBW][NBW + 1];
+  __shared__ double Ws[16][NBW + 1];
+  for (int e = tid; e < NBW * NBW; e += 256) Ts[e / NBW][e % NBW] = TB[e];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = tid + 256 * i, r = e / NBW, c = e % NBW;
+    const bool ok = row0 + r < nt && c < nv;
+    double a = 0.0;
+    for (int sl = 0; sl < S; ++sl) a += ok ? P[sl * snn + (long)(row0 + r) * nv + c] : 0.0;
+    Ws[r][c] = a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = tid + 256 * i, r = e / NBW, c = e % NBW;
+    if (row0 + r >= nt || c >= nv) continue;
+    double a = 0.0;
+    for (int j = 0; j < nv; ++j) a += Ws[r][j] * (TRANS_T ? Ts[c][j] : Ts[j][c]);
+    W2[(long)(row0 + r) * NBW + c] = a;
+  }
+}
+
 // R (k x k, row-major, zero below the diagonal) from the factored Xt
 __global__ void qr_extract_r_kernel(const double* Xt_all, double* R_all, int m, int k, long sX) {
   const int b = blockIdx.y;
@@ -422,6 +458,15 @@ __global__ void qr_eye_kernel(double* Qt_all, int m, int k, long sX) {
 }
 
 static int grid_of(long n) { return (int)std::min<long>((n + 255) / 256, 4096); }
+
+// K slices of W = Y V^T: enough workgroups to fill the chip, slices of at
+// least 256 entries
+static int w_slices(int nt, int len, int batch) {
+  const int tiles = (nt + 63) / 64;
+  int S = (384 + tiles * batch - 1) / (tiles * batch);
+  S = std::min(S, std::min(QR_SMAX, len / 256));
+  return std::max(S, 1);
+}
 
 hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R, double* Qt, void* work) {
   if (m < k || k < 1 || batch < 1) return hipErrorInvalidValue;
@@ -520,9 +565,13 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
     if (nt <= 0 || e != hipSuccess) continue;
     // Xt_trail (nt x rows) -= ((Xt_trail V^T) T) V
     double* Y = Xt + (long)j1 * m + j0;
-    e = gemm_f64(s, false, true, nt, nv, rows, 1.0, Y, m, L.sX, Vb, m, L.sX, 0.0, Wb, NBW, L.sW, batch);
-    if (e == hipSuccess)
-      e = gemm_f64(s, false, false, nt, nv, nv, 1.0, Wb, NBW, L.sW, TBb, NBW, L.sTB, 0.0, W2b, NBW, L.sW, batch);
+    const int S = w_slices(nt, rows, batch);
+    e = gemm_f64_slices(s, false, true, nt, nv, rows, Y, m, L.sX, Vb, m, L.sX, Wb, S, batch);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(qr_w2_kernel<false>, dim3((nt + 15) / 16, batch), dim3(256), 0, s, (const double*)Wb, S, nt,
+                         nv, (const double*)TBb, L.sTB, W2b, L.sW);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess)
       e = gemm_f64(s, false, false, nt, rows, nv, -1.0, W2b, NBW, L.sW, Vb, m, L.sX, 1.0, Y, m, L.sX, batch);
   }
@@ -541,9 +590,13 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
     const double* TBb = TB + (long)bi * NBW * NBW;
     double* Y = Qt + (long)j0 * m + j0;
     // Qt_sub (rows j0.., columns j0..) -= ((Qt_sub V^T) T^T) V
-    e = gemm_f64(s, false, true, nt, nv, rows, 1.0, Y, m, L.sX, Vb, m, L.sX, 0.0, Wb, NBW, L.sW, batch);
-    if (e == hipSuccess)
-      e = gemm_f64(s, false, true, nt, nv, nv, 1.0, Wb, NBW, L.sW, TBb, NBW, L.sTB, 0.0, W2b, NBW, L.sW, batch);
+    const int S = w_slices(nt, rows, batch);
+    e = gemm_f64_slices(s, false, true, nt, nv, rows, Y, m, L.sX, Vb, m, L.sX, Wb, S, batch);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(qr_w2_kernel<true>, dim3((nt + 15) / 16, batch), dim3(256), 0, s, (const double*)Wb, S, nt,
+                         nv, TBb, L.sTB, W2b, L.sW);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess)
       e = gemm_f64(s, false, false, nt, rows, nv, -1.0, W2b, NBW, L.sW, Vb, m, L.sX, 1.0, Y, m, L.sX, batch);
   }
