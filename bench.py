@@ -74,7 +74,37 @@ def parse():
     ap.add_argument("--fwd-sweeps", type=int, default=4, help="timed forward-only sweeps for sweeps/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device once (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+# HBM traffic of the dominant kernel class, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of this script (scaled by the counters' reading for a copy of
+# known size); valid only while the kernel's source is the one measured.
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCE = {"jacobi_rotate": "paper_2502_10298_amd/csrc/svd.hip",
+                 "jacobi_gram": "paper_2502_10298_amd/csrc/svd.hip",
+                 "jacobi_solve": "paper_2502_10298_amd/csrc/svd.hip"}
+
+
+def measured_traffic(kernel: str):
+    import hashlib
+    path = os.path.join(TRAFFIC_DIR, f"traffic_{kernel}_{WORKLOAD}.txt")
+    if kernel not in KERNEL_SOURCE or not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = open(os.path.join(ROOT, KERNEL_SOURCE[kernel]), "rb").read()
+    if fields.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(threads: int) -> dict:
@@ -115,6 +145,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 4}), flush=True)
+        return
     w = inp.WORKLOADS[WORKLOAD]
     chi = w["chi"]
     dev = torch.device("cuda:0")
@@ -163,7 +201,8 @@ def main():
     ms, launches, flops, nbytes = timing[dom]
     total_ms = sum(v[0] for v in timing.values())
     roof = roofline_of(dom, ms, launches, flops, nbytes)
-    roof.update({"traffic": None, "kernel": dom, "launches": int(launches),
+    roof.update({"traffic": measured_traffic(dom), "kernel": dom, "launches": int(launches),
+                 "algorithmic_bytes_per_launch": nbytes / launches if launches else None,
                  "avg_launch_us": 1e3 * ms / launches if launches else None,
                  "share_of_timed_kernels": ms / total_ms if total_ms else None,
                  "classes": {k: dict(ms=v[0], launches=int(v[1]), **{kk: vv for kk, vv in
