@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
+#include <vector>
 
 namespace sctm {
 
@@ -624,6 +626,22 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
     if (err != hipSuccess) return err;
     running = 0;
     for (int b = 0; b < batch; ++b) running += host_flags[b] ? 0 : 1;
+    static const int conv_trace = [] {
+      const char* e = std::getenv("SPLITCTM_SVD_TRACE");
+      return e ? std::atoi(e) : 0;
+    }();
+    if (conv_trace >= 2) {   // largest off-diagonal measure of the sweep, per batch entry
+      std::vector<double> ho((size_t)L.sOff * batch);
+      err = hipMemcpy(ho.data(), off, sizeof(double) * ho.size(), hipMemcpyDeviceToHost);
+      if (err != hipSuccess) return err;
+      fprintf(stderr, "[svd] n=%d sweep %d off:", n, sw + 1);
+      for (int b = 0; b < batch; ++b) {
+        double mx = 0.0;
+        for (long i = 0; i < L.sOff; ++i) mx = std::max(mx, ho[(size_t)b * L.sOff + i]);
+        fprintf(stderr, " %.1e", mx);
+      }
+      fprintf(stderr, "\n");
+    }
     if (running == 0) break;
   }
   if (KernelTimer* tm = kernel_timer()) {   // exact work of the rotations that ran
