@@ -17,6 +17,94 @@ static inline int grid_for(long n, int per = 256, int cap = 65535 * 4) {
 }
 
 // ---------------------------------------------------------------------------
+// Index permutation.  Below 2^31 elements all index arithmetic is 32-bit,
+// with the per-axis divisions replaced by multiply-high division by invariant
+// integers (Granlund and Montgomery, 1994): for d >= 1, l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1, and n / d = (t + ((n - t) >> min(l, 1)))
+// >> max(l - 1, 0) with t = umulhi(m, n), exact for every 32-bit n.
+struct FastDiv {
+  unsigned d, m, s1, s2;
+};
+
+static FastDiv make_fastdiv(unsigned d) {
+  unsigned l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  FastDiv f;
+  f.d = d;
+  f.m = (unsigned)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+  f.s1 = l < 1 ? l : 1;
+  f.s2 = l > 1 ? l - 1 : 0;
+  return f;
+}
+
+__device__ __forceinline__ unsigned fast_div(unsigned n, const FastDiv& f) {
+  const unsigned t = __umulhi(f.m, n);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+struct PermGeneric {
+  int rank;
+  FastDiv dv[12];         // output dimensions
+  unsigned istr[12];      // input stride of each output axis
+};
+
+// any permutation, one output element per thread (writes coalesced)
+template <typename T>
+__global__ void permute32_kernel(const T* __restrict__ in, T* __restrict__ out, PermGeneric d, unsigned n, bool acc) {
+  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    unsigned rem = i, off = 0;
+    for (int ax = d.rank - 1; ax >= 0; --ax) {
+      const unsigned q = fast_div(rem, d.dv[ax]);
+      off += (rem - q * d.dv[ax].d) * d.istr[ax];
+      rem = q;
+    }
+    out[i] = acc ? out[i] + in[off] : in[off];
+  }
+}
+
+struct PermTiled {
+  unsigned DX, DY;        // output axis X (last, output stride 1) and axis Y (input stride 1)
+  unsigned sx, oy;        // input stride of X, output stride of Y
+  int nrest;              // the other axes
+  unsigned nr;            // product of their dimensions
+  FastDiv rdv[12];
+  unsigned rin[12], rout[12];
+};
+
+// permutation whose innermost input and output axes differ: 32 x 32 tiles
+// of (X, Y) through LDS, read along Y (input-contiguous) and written along X
+// (output-contiguous); grid z runs over the other axes.
+template <typename T>
+__global__ void permute_tiled_kernel(const T* __restrict__ in, T* __restrict__ out, PermTiled d, bool acc) {
+  __shared__ T tile[32][33];
+  const unsigned x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+  const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+  for (unsigned z = blockIdx.z; z < d.nr; z += gridDim.z) {
+    unsigned rem = z, bin = 0, bout = 0;
+    for (int ax = d.nrest - 1; ax >= 0; --ax) {
+      const unsigned q = fast_div(rem, d.rdv[ax]);
+      const unsigned c = rem - q * d.rdv[ax].d;
+      bin += c * d.rin[ax];
+      bout += c * d.rout[ax];
+      rem = q;
+    }
+    for (int j = ty; j < 32; j += 8) {
+      const unsigned x = x0 + j, y = y0 + tx;
+      if (x < d.DX && y < d.DY) tile[j][tx] = in[bin + x * d.sx + y];
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+      const unsigned y = y0 + j, x = x0 + tx;
+      if (x < d.DX && y < d.DY) {
+        const unsigned o = bout + y * d.oy + x;
+        out[o] = acc ? out[o] + tile[tx][j] : tile[tx][j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// 64-bit fallback for tensors of 2^31 elements or more
 template <typename T>
 __global__ void permute_kernel(const T* __restrict__ in, T* __restrict__ out, PermDesc d, long n,
                                bool acc) {
@@ -55,6 +143,46 @@ __global__ void transpose_kernel(const T* __restrict__ in, T* __restrict__ out, 
   }
 }
 
+template <typename T>
+static void launch_permute32(hipStream_t s, const void* in, void* out, const PermDesc& d, long n, bool acc) {
+  // output strides (row-major over out_dims)
+  long ost[12];
+  ost[d.rank - 1] = 1;
+  for (int i = d.rank - 2; i >= 0; --i) ost[i] = ost[i + 1] * d.out_dims[i + 1];
+  int yax = -1;
+  for (int i = 0; i < d.rank; ++i)
+    if (d.in_strides_perm[i] == 1) yax = i;
+  // tiles only pay when both axes fill them
+  if (yax >= 0 && yax != d.rank - 1 && d.out_dims[d.rank - 1] >= 32 && d.out_dims[yax] >= 32) {
+    PermTiled t;
+    t.DX = (unsigned)d.out_dims[d.rank - 1];
+    t.DY = (unsigned)d.out_dims[yax];
+    t.sx = (unsigned)d.in_strides_perm[d.rank - 1];
+    t.oy = (unsigned)ost[yax];
+    t.nrest = 0;
+    t.nr = 1;
+    for (int i = 0; i < d.rank - 1; ++i) {
+      if (i == yax) continue;
+      t.rdv[t.nrest] = make_fastdiv((unsigned)d.out_dims[i]);
+      t.rin[t.nrest] = (unsigned)d.in_strides_perm[i];
+      t.rout[t.nrest] = (unsigned)ost[i];
+      t.nr *= (unsigned)d.out_dims[i];
+      ++t.nrest;
+    }
+    dim3 g((t.DX + 31) / 32, (t.DY + 31) / 32, t.nr < 65535u ? t.nr : 65535u);
+    hipLaunchKernelGGL(permute_tiled_kernel<T>, g, dim3(32, 8), 0, s, (const T*)in, (T*)out, t, acc);
+    return;
+  }
+  PermGeneric gd;
+  gd.rank = d.rank;
+  for (int i = 0; i < d.rank; ++i) {
+    gd.dv[i] = make_fastdiv((unsigned)d.out_dims[i]);
+    gd.istr[i] = (unsigned)d.in_strides_perm[i];
+  }
+  hipLaunchKernelGGL(permute32_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, (const T*)in, (T*)out, gd,
+                     (unsigned)n, acc);
+}
+
 hipError_t permute(hipStream_t s, int esize, const void* in, void* out, const PermDesc& d, long n,
                    bool accumulate) {
   if (n <= 0) return hipSuccess;
@@ -86,6 +214,13 @@ hipError_t permute(hipStream_t s, int esize, const void* in, void* out, const Pe
         return hipGetLastError();
       }
     }
+  }
+  if (n < (1L << 31) && d.rank <= 12) {
+    if (esize == 8)
+      launch_permute32<double>(s, in, out, d, n, accumulate);
+    else
+      launch_permute32<float>(s, in, out, d, n, accumulate);
+    return hipGetLastError();
   }
   int g = grid_for(n);
   if (esize == 8)
