@@ -11,7 +11,8 @@ resident in HBM.
 
 Prints one JSON line (see the keys below); `roofline` is taken from the
 library's own HIP-event timing of the dominant kernel class over the timed
-steps, `cpu_baseline` from the FP64 CPU oracle on a bounded sample (one
+steps (events on every `--timing-stride`-th launch of each class, so that the
+events' host cost stays out of the timed run), `cpu_baseline` from the FP64 CPU oracle on a bounded sample (one
 column of one left move at the same sizes).
 """
 from __future__ import annotations
@@ -74,6 +75,8 @@ def parse():
     ap.add_argument("--fwd-sweeps", type=int, default=4, help="timed forward-only sweeps for sweeps/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--timing-stride", type=int, default=16,
+                    help="HIP events on every k-th launch of each kernel class in the timed steps")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device once (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -174,7 +177,7 @@ def main():
     obj.env_import(obj.env_export())
     torch.cuda.synchronize()
 
-    obj.kernel_timing_enable(True)
+    obj.kernel_timing_enable(True, stride=args.timing_stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e = None
@@ -203,6 +206,7 @@ def main():
     roof = roofline_of(dom, ms, launches, flops, nbytes)
     roof.update({"traffic": measured_traffic(dom), "kernel": dom, "launches": int(launches),
                  "algorithmic_bytes_per_launch": nbytes / launches if launches else None,
+                 "event_sample_stride": args.timing_stride,
                  "avg_launch_us": 1e3 * ms / launches if launches else None,
                  "share_of_timed_kernels": ms / total_ms if total_ms else None,
                  "classes": {k: dict(ms=v[0], launches=int(v[1]), **{kk: vv for kk, vv in

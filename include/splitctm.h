@@ -152,13 +152,16 @@ ctm_status ctm_debug_qr(int m, int k, int batch, double* Xt, double* R, double* 
 ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S, double* V, void* work,
                          int* sweeps, void* hip_stream);
 
-/* Kernel timing (diagnostics): when enabled, every launch of a timed kernel
- * class made by this context carries a start and a stop event recorded by the
- * runtime at the start and the end of that kernel on the context's stream;
- * after each call the elapsed times are added up per class.  Enabling (or
+/* Kernel timing (diagnostics): with on = k >= 1, every k-th launch of each
+ * timed kernel class made by this context carries a start and a stop event
+ * recorded by the runtime at the start and the end of that kernel on the
+ * context's stream (k = 1: every launch; larger k keeps the events' own host
+ * cost out of the run); on = 0 disables, on < 0 is CTM_EINVAL.  After each
+ * call the sampled elapsed times are added up per class.  Enabling (or
  * disabling) resets the totals.  Classes: 0 GEMM FP64, 1 GEMM FP32, 2 GEMM
  * BF16x3, 3 Jacobi Gram matrices, 4 Jacobi 32 x 32 eigensolves, 5 Jacobi
- * rotations of G and V, 6 GEMM BF16x6.  *ms = summed kernel time, *launches = number of
+ * rotations of G and V, 6 GEMM BF16x6.  *ms = kernel time (the mean of the
+ * sampled launches times the number of launches), *launches = number of
  * launches, *flops and *bytes = algorithmic work and memory traffic of those
  * launches (GEMM: 2 M N K flops and the operands read and written once;
  * Gram: the pairs' columns read once; eigensolve: partial Gram matrices read

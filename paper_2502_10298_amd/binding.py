@@ -215,8 +215,9 @@ class SplitCTM:
         if st != CTM_OK:
             raise CtmError(st, "ctm_env_import")
 
-    def kernel_timing_enable(self, on=True):
-        st = lib().ctm_kernel_timing_enable(self.h, int(on))
+    def kernel_timing_enable(self, on=True, stride=1):
+        """Event timing of every `stride`-th launch per kernel class (off: on=False)."""
+        st = lib().ctm_kernel_timing_enable(self.h, int(stride) if on else 0)
         if st != CTM_OK:
             raise CtmError(st, "ctm_kernel_timing_enable")
 

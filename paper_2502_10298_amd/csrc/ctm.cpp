@@ -1179,16 +1179,17 @@ ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S
 }
 
 ctm_status ctm_kernel_timing_enable(ctm_ctx* c, int on) {
-  if (!c) return CTM_EINVAL;
+  if (!c || on < 0) return CTM_EINVAL;
   c->timing = on != 0;
   c->timer.reset();
+  c->timer.stride = on > 0 ? on : 1;
   return CTM_OK;
 }
 
 ctm_status ctm_kernel_timing(ctm_ctx* c, int kernel_class, double* ms, double* launches, double* flops,
                              double* bytes) {
   if (!c || kernel_class < 0 || kernel_class >= KC_COUNT) return CTM_EINVAL;
-  if (ms) *ms = c->timer.ms[kernel_class];
+  if (ms) *ms = c->timer.ms(kernel_class);
   if (launches) *launches = c->timer.launches[kernel_class];
   if (flops) *flops = c->timer.flops[kernel_class];
   if (bytes) *bytes = c->timer.bytes[kernel_class];

@@ -1,9 +1,12 @@
 // Timing of selected kernel launches (diagnostics).  When a timer is
-// installed for the calling thread, every launch of a timed kernel class goes
-// through hipExtLaunchKernelGGL with a start and a stop event, which the
-// runtime records at the start and the end of that kernel's execution on its
-// stream; collect() (after the stream has been synchronised) adds the
-// elapsed times and the algorithmic work of the launches to per-class totals.
+// installed for the calling thread, every stride-th launch of each timed
+// kernel class goes through hipExtLaunchKernelGGL with a start and a stop
+// event, which the runtime records at the start and the end of that kernel's
+// execution on its stream; the other launches go out plain (events on every
+// launch would add their own host cost to the run being measured).
+// collect() (after the stream has been synchronised) adds up the sampled
+// times; the per-class time is the sampled mean times the number of
+// launches, and the algorithmic work covers every launch.
 #pragma once
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -28,12 +31,13 @@ struct KernelTimer {
   struct Rec {
     int kind;
     hipEvent_t a, b;
-    double flops, bytes;
   };
+  int stride = 1;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<Rec> pending;
-  double ms[KC_COUNT] = {};
+  double sampled_ms[KC_COUNT] = {};
+  double sampled[KC_COUNT] = {};
   double flops[KC_COUNT] = {};
   double bytes[KC_COUNT] = {};
   double launches[KC_COUNT] = {};
@@ -46,11 +50,17 @@ struct KernelTimer {
     }
     return pool[used++];
   }
+  // counts the launch and its work; true (with the two events) when it is sampled
   bool events(int kind, double f, double by, hipEvent_t& a, hipEvent_t& b) {
+    flops[kind] += f;
+    bytes[kind] += by;
+    const long k = (long)launches[kind];
+    launches[kind] += 1;
+    if (k % stride != 0) return false;
     a = next();
     b = next();
     if (!a || !b) return false;
-    pending.push_back({kind, a, b, f, by});
+    pending.push_back({kind, a, b});
     return true;
   }
   void add(int kind, double f, double by) {
@@ -61,19 +71,19 @@ struct KernelTimer {
     for (const Rec& r : pending) {
       float t = 0.f;
       if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
-        ms[r.kind] += t;
-        flops[r.kind] += r.flops;
-        bytes[r.kind] += r.bytes;
-        launches[r.kind] += 1;
+        sampled_ms[r.kind] += t;
+        sampled[r.kind] += 1;
       }
     }
     pending.clear();
     used = 0;
   }
+  // estimated total kernel time of a class: sampled mean x launches
+  double ms(int kind) const { return sampled[kind] > 0 ? sampled_ms[kind] / sampled[kind] * launches[kind] : 0.0; }
   void reset() {
     pending.clear();
     used = 0;
-    for (int k = 0; k < KC_COUNT; ++k) ms[k] = flops[k] = bytes[k] = launches[k] = 0;
+    for (int k = 0; k < KC_COUNT; ++k) sampled_ms[k] = sampled[k] = flops[k] = bytes[k] = launches[k] = 0;
   }
   ~KernelTimer() {
     for (hipEvent_t e : pool) hipEventDestroy(e);

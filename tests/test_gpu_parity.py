@@ -305,3 +305,29 @@ def test_not_converged_is_reported():
     assert st == b.CTM_ENOTCONV and n == 1
     e, _ = obj.energy(inp.heisenberg_h())   # environment still usable
     assert math.isfinite(e)
+
+
+def test_kernel_timing_sampling():
+    """Sampled event timing counts every launch and its work, and its time
+    estimate (sampled mean x launches) agrees with timing every launch."""
+    A = torch.tensor(inp.workload_peps("d2_D2_chi8"), device=DEV)
+    _say("kernel timing sampling")
+    obj = b.SplitCTM(A, 8, prec="fp64")
+    obj.sweep(3)
+    env = obj.env_export()
+    res = {}
+    for stride in (1, 4):
+        obj.env_import(env)
+        torch.cuda.synchronize()
+        obj.kernel_timing_enable(True, stride=stride)
+        obj.sweep(3)
+        res[stride] = obj.kernel_timing()
+        obj.kernel_timing_enable(False)
+    for k in ("gemm_fp64", "jacobi_gram", "jacobi_solve", "jacobi_rotate"):
+        ms1, n1, f1, b1 = res[1][k]
+        ms4, n4, f4, b4 = res[4][k]
+        assert n1 == n4 > 0 and f1 == f4 and b1 == b4, k
+        assert ms1 > 0 and 0.5 * ms1 < ms4 < 2.0 * ms1, (k, ms1, ms4)
+    with pytest.raises(b.CtmError):
+        obj.kernel_timing_enable(True, stride=-1)
+    obj.close()
