@@ -352,3 +352,22 @@ def test_gradient_matches_finite_differences_and_scale_invariance():
         fd = og.central_difference4(A, env0, chi, chi, ns, h, d, step=1e-5)
         an = float((g * d).sum())
         assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3 * np.linalg.norm(g)), (fd, an)
+
+
+@pytest.mark.slow
+def test_interlayer_bond_below_environment_bond_converges():
+    """Sec. III, independent chi_I: at fixed chi_E the split energy approaches
+    the conventional CTMRG energy monotonically as chi_I grows to chi_E."""
+    A_np = inp.peps_gaussian(7, 1, 1, 2, 2)
+    h = inp.heisenberg_h_rotated()
+    env_c, Ad = cc.run(A_np, 16, 40)
+    e_ref = cc.energy(env_c, Ad, 1, 1, h)
+    A = sc.peps_from_numpy(A_np)
+    diffs = []
+    for chi_I in (2, 4, 8):
+        env = sc.init_identity(1, 1, 2)
+        env, _, _ = sc.run(env, A, 1, 1, 8, chi_I, 40)
+        es, _ = sc.energy(env, A, 1, 1, h)
+        diffs.append(abs(float(es) - e_ref) / abs(e_ref))
+    assert diffs[0] > diffs[1] > diffs[2]
+    assert diffs[2] < 1e-5
