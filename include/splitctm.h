@@ -27,7 +27,10 @@
  *     calls on one context are not reentrant.
  *   - Projector SVDs, truncation, normalisation reductions and the final
  *     energy reduction are always FP64; `contract_prec` sets the precision of
- *     the tensor-network contractions.
+ *     the tensor-network contractions.  The one-sided Jacobi SVD runs to
+ *     working accuracy with FP64 contractions and to a relative
+ *     off-orthogonality of 1e-10 with FP32, BF16x3 or BF16x6 contractions,
+ *     whose own rounding is larger.
  *
  * Errors: every call returns a ctm_status.  CTM_EINVAL = bad argument or
  * workspace too small (no side effects); CTM_ENUMERIC = non-finite values or a
