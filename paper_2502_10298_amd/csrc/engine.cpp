@@ -1047,17 +1047,32 @@ void Engine::proj_backward(TapeRec& r) {
   if (!dry && ok()) check(add_transposed(s, nb, chi, c2, C2.f64(), Q1.f64()));   // Q1[c][b] += C2[b][c]
   if (!dry && ok()) check(copy_cols(s, nb, chi, c2, C1.f64(), Q2.f64()));         // Q2 = C1[:, :c2]
   if (nb > c2) gemm(false, false, nb, c2, nb - c2, 1.0, ps.U, c2, nb, Ileft, 0, c2, 1.0, Q2, 0, c2);
-  // Mbar = U[:, :c2] Q1 + Q2 V[:, :c2]^T
-  Ten Mb = alloc(F64, {nb, nb});
-  gemm(false, false, nb, nb, c2, 1.0, ps.U, 0, nb, Q1, 0, nb, 0.0, Mb, 0, nb);
-  gemm(false, true, nb, nb, c2, 1.0, Q2, 0, c2, ps.V, 0, nb, 1.0, Mb, 0, nb);
-  // rho bars from M
+  // Mbar = U_c Q1 + Q2 V_c^T (U_c, V_c: the first c2 columns) has rank <= 2 c2;
+  // the rho bars take it in this factored form (never the b x b matrix):
+  // O(na b c2) instead of O(na b^2)
+  Ten A1 = alloc(F64, {na, c2}), A2 = alloc(F64, {na, c2});
   if (rows) {   // M = rB^T rT  (rho: na x nb)
-    gemm(false, true, na, nb, nb, 1.0, ps.rT, 0, nb, Mb, 0, nb, 1.0, rBb, 0, nb);   // rBb += rT Mb^T
-    gemm(false, false, na, nb, nb, 1.0, ps.rB, 0, nb, Mb, 0, nb, 1.0, rTb, 0, nb);  // rTb += rB Mb
-  } else {      // M = rB rT^T  (rho: nb x na)
-    gemm(false, false, nb, na, nb, 1.0, Mb, 0, nb, ps.rT, 0, na, 1.0, rBb, 0, na);  // rBb += Mb rT
-    gemm(true, false, nb, na, nb, 1.0, Mb, 0, nb, ps.rB, 0, na, 1.0, rTb, 0, na);   // rTb += Mb^T rB
+    // rBb += rT Mb^T = (rT Q1^T) U_c^T + (rT V_c) Q2^T
+    gemm(false, true, na, c2, nb, 1.0, ps.rT, 0, nb, Q1, 0, nb, 0.0, A1, 0, c2);
+    gemm(false, false, na, c2, nb, 1.0, ps.rT, 0, nb, ps.V, 0, nb, 0.0, A2, 0, c2);
+    gemm(false, true, na, nb, c2, 1.0, A1, 0, c2, ps.U, 0, nb, 1.0, rBb, 0, nb);
+    gemm(false, true, na, nb, c2, 1.0, A2, 0, c2, Q2, 0, c2, 1.0, rBb, 0, nb);
+    // rTb += rB Mb = (rB U_c) Q1 + (rB Q2) V_c^T
+    gemm(false, false, na, c2, nb, 1.0, ps.rB, 0, nb, ps.U, 0, nb, 0.0, A1, 0, c2);
+    gemm(false, false, na, c2, nb, 1.0, ps.rB, 0, nb, Q2, 0, c2, 0.0, A2, 0, c2);
+    gemm(false, false, na, nb, c2, 1.0, A1, 0, c2, Q1, 0, nb, 1.0, rTb, 0, nb);
+    gemm(false, true, na, nb, c2, 1.0, A2, 0, c2, ps.V, 0, nb, 1.0, rTb, 0, nb);
+  } else {      // M = rB rT^T  (rho: nb x na); A1, A2 hold c2 x na products here
+    // rBb += Mb rT = U_c (Q1 rT) + Q2 (V_c^T rT)
+    gemm(false, false, c2, na, nb, 1.0, Q1, 0, nb, ps.rT, 0, na, 0.0, A1, 0, na);
+    gemm(true, false, c2, na, nb, 1.0, ps.V, 0, nb, ps.rT, 0, na, 0.0, A2, 0, na);
+    gemm(false, false, nb, na, c2, 1.0, ps.U, 0, nb, A1, 0, na, 1.0, rBb, 0, na);
+    gemm(false, false, nb, na, c2, 1.0, Q2, 0, c2, A2, 0, na, 1.0, rBb, 0, na);
+    // rTb += Mb^T rB = Q1^T (U_c^T rB) + V_c (Q2^T rB)
+    gemm(true, false, c2, na, nb, 1.0, ps.U, 0, nb, ps.rB, 0, na, 0.0, A1, 0, na);
+    gemm(true, false, c2, na, nb, 1.0, Q2, 0, c2, ps.rB, 0, na, 0.0, A2, 0, na);
+    gemm(true, false, nb, na, c2, 1.0, Q1, 0, nb, A1, 0, na, 1.0, rTb, 0, na);
+    gemm(false, false, nb, na, c2, 1.0, ps.V, 0, nb, A2, 0, na, 1.0, rTb, 0, na);
   }
   Ten gT = grad(r.in[0]);
   Ten gB = grad(r.in[1]);
