@@ -39,8 +39,7 @@ MFMA_PEAKS = {
     "gemm_fp32": (157.3, "fp32 MFMA"),
     "gemm_bf16x3": (2500.0 / 3.0, "bf16 MFMA 2500 / 3 products"),
     "gemm_bf16x6": (2500.0 / 6.0, "bf16 MFMA 2500 / 6 products"),
-    "jacobi_gram": (78.6, "fp64 MFMA"),
-    "jacobi_solve": (78.6, "fp64 MFMA"),
+    "jacobi_pair": (78.6, "fp64 MFMA"),
     "jacobi_rotate": (78.6, "fp64 MFMA"),
 }
 
@@ -87,8 +86,7 @@ def parse():
 # known size); valid only while the kernel's source is the one measured.
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCE = {"jacobi_rotate": "paper_2502_10298_amd/csrc/svd.hip",
-                 "jacobi_gram": "paper_2502_10298_amd/csrc/svd.hip",
-                 "jacobi_solve": "paper_2502_10298_amd/csrc/svd.hip"}
+                 "jacobi_pair": "paper_2502_10298_amd/csrc/svd.hip"}
 
 
 def measured_traffic(kernel: str):

@@ -162,13 +162,14 @@ ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S
  * cost out of the run); on = 0 disables, on < 0 is CTM_EINVAL.  After each
  * call the sampled elapsed times are added up per class.  Enabling (or
  * disabling) resets the totals.  Classes: 0 GEMM FP64, 1 GEMM FP32, 2 GEMM
- * BF16x3, 3 Jacobi Gram matrices, 4 Jacobi 32 x 32 eigensolves, 5 Jacobi
- * rotations of G and V, 6 GEMM BF16x6.  *ms = kernel time (the mean of the
+ * BF16x3, 3 Jacobi pair kernels (Gram matrix, test and 32 x 32
+ * eigensolve of every block pair), 4 unused, 5 Jacobi rotations of G and V,
+ * 6 GEMM BF16x6.  *ms = kernel time (the mean of the
  * sampled launches times the number of launches), *launches = number of
  * launches, *flops and *bytes = algorithmic work and memory traffic of those
  * launches (GEMM: 2 M N K flops and the operands read and written once;
- * Gram: the pairs' columns read once; eigensolve: partial Gram matrices read
- * and rotations written; rotation: the rotated columns of G and V read and
+ * pair kernels: the pairs' columns read once and the rotations written;
+ * rotation: the rotated columns of G and V read and
  * written once, counted on the device for the pairs that were rotated). */
 ctm_status ctm_kernel_timing_enable(ctm_ctx* ctx, int on);
 ctm_status ctm_kernel_timing(ctm_ctx* ctx, int kernel_class, double* ms, double* launches, double* flops,

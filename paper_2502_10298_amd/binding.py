@@ -24,7 +24,7 @@ EXPORTED = ("ctm_workspace_size", "ctm_init", "ctm_sweep", "ctm_projectors", "ct
             "ctm_energy", "ctm_energy_grad", "ctm_env_elems", "ctm_env_export", "ctm_env_import",
             "ctm_last_stats", "ctm_debug_gemm_work_bytes", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd", "ctm_debug_qr_work_bytes", "ctm_debug_qr",
             "ctm_kernel_timing_enable", "ctm_kernel_timing", "ctm_destroy", "ctm_strerror")
-KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "gemm_bf16x3": 2, "jacobi_gram": 3, "jacobi_solve": 4,
+KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "gemm_bf16x3": 2, "jacobi_pair": 3,
                   "jacobi_rotate": 5, "gemm_bf16x6": 6}
 
 

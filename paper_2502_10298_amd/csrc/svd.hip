@@ -112,16 +112,12 @@ __device__ inline void circle_pair(int players, int round, int idx, int& a, int&
   }
 }
 
-// One round of the tournament is three launches, each filling the chip:
-//   gram:   grid (pair, 256-entry chunk of the column length): the partial
-//           32 x 32 Gram matrix of the pair's columns over the chunk, on the
-//           FP64 matrix cores (v_mfma_f64_16x16x4: A lane l holds
-//           A[l%16][l/16], B lane l holds B[l/16][l%16], D lane l register r
-//           holds D[4r + l/16][l%16]);
-//   solve:  grid (pair): sums the partials in a fixed order (the result does
-//           not depend on scheduling), tests the pair and, unless it is
-//           converged, diagonalises the Gram matrix by cyclic two-sided
-//           Jacobi in LDS, giving the 32 x 32 rotation W;
+// One round of the tournament is two launches:
+//   pair:   grid (pair): the 32 x 32 Gram matrix of the pair's columns on the
+//           FP64 matrix cores, the convergence test and, unless the pair is
+//           converged, its diagonalisation by cyclic two-sided Jacobi in LDS,
+//           giving the 32 x 32 rotation W (one workgroup per pair, so the
+//           Gram matrix is summed in a fixed order and never leaves the chip);
 //   rotate: grid (pair, chunk of G or of V): new columns = old columns W,
 //           again on the matrix cores.
 //
@@ -134,169 +130,163 @@ __device__ inline void circle_pair(int players, int round, int idx, int& a, int&
 // for a numerically rank-deficient M.
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-static constexpr int JCH = 256;      // column-length entries per chunk (4 waves x 64)
-
-__global__ __launch_bounds__(256) void jacobi_gram_kernel(const double* Gt_all, int m, int np, int round, long sG,
-                                                          double* part_all, int nchunk, const int* done) {
-  const int b = blockIdx.z;
-  if (done[b]) return;
-  const double* Gt = Gt_all + b * sG;
-  const int nb = np / JW, pairs = nb / 2;
-  const int pr = blockIdx.x, ch = blockIdx.y;
-  int p, q;
-  circle_pair(nb, round, pr, p, q);
-  __shared__ double sm[4 * 2 * JP * 17];   // staging [wave][2 subs][32][17], then the wave partials [4][1024]
-  __shared__ int rowidx[JP];
-  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
-  if (tid < JP) rowidx[tid] = (tid < JW) ? p * JW + tid : q * JW + (tid - JW);
-  __syncthreads();
-  d4v acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0, 0, 0, 0};
-  const int c0 = ch * JCH + wv * 64;
-  // all 4 x 16 entries of the wave's 64-entry slice in flight at once; staged
-  // through LDS two 16-entry subs at a time
-  double v[4][8];
-#pragma unroll
-  for (int sub = 0; sub < 4; ++sub)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int r = i * 4 + (l >> 4), c = c0 + sub * 16 + (l & 15);
-      v[sub][i] = (c < m) ? Gt[(long)rowidx[r] * m + c] : 0.0;
-    }
-#pragma unroll
-  for (int half = 0; half < 2; ++half) {
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) sm[((wv * 2 + s2) * JP + i * 4 + (l >> 4)) * 17 + (l & 15)] = v[2 * half + s2][i];
-    __syncthreads();
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const double* buf = sm + (wv * 2 + s2) * JP * 17;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kc = kk * 4 + (l >> 4);
-        const double a0 = buf[(l & 15) * 17 + kc], a1 = buf[(16 + (l & 15)) * 17 + kc];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, acc[0][1], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc[1][1], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-  // (the lower off-diagonal tile (1, 0) is the transpose of (0, 1) and is not formed)
-  for (int ti = 0; ti < 2; ++ti)
-    for (int tj = 0; tj < 2; ++tj)
-      if (ti <= tj)
-        for (int r = 0; r < 4; ++r) sm[wv * 1024 + ((ti * 2 + tj) * 4 + r) * 64 + l] = acc[ti][tj][r];
-  __syncthreads();
-  double* out = part_all + (((long)b * pairs + pr) * nchunk + ch) * 1024;
-  for (int e = tid; e < 1024; e += 256)
-    if ((e >> 8) != 2) out[e] = (sm[e] + sm[1024 + e]) + (sm[2048 + e] + sm[3072 + e]);
-}
-
 // Jacobi rotation that zeroes the (a, c) entry of a symmetric 2 x 2 block:
 // new row a = c row_a - s row_c, new row c = s row_a + c row_c (same on
 // columns).  Below the threshold the identity is returned.  With D = h_cc -
-// h_aa and E = 2 h_ac the tangent of the smaller angle is
-// t = sign(D E) |E| / (|D| + sqrt(D^2 + E^2)).  The square root and the
-// quotient come from the hardware reciprocal square root and reciprocal,
-// each refined by a Newton step (t need not be exact: any t gives an exact
-// rotation), and c = 1 / sqrt(1 + t^2) from the reciprocal square root
-// refined by two Newton steps (c^2 + s^2 = 1 to working accuracy, which keeps
-// W orthogonal).  Branch-free, so that the two rotations a thread needs per
-// round overlap.
+// h_aa, E = 2 h_ac and r = sqrt(D^2 + E^2), the smaller angle has tangent
+// t = sign(D E) |E| / (|D| + r); writing d = |D| + r, the pair
+//   c = d / sqrt(d^2 + E^2),  s = sign(D E) |E| / sqrt(d^2 + E^2)
+// has that tangent, and c^2 + s^2 = 1 holds to the accuracy of the one
+// reciprocal square root, whatever the accuracy of r (any t gives an exact
+// rotation; r only steers how well the entry is zeroed).  r comes from the
+// hardware reciprocal square root with one Newton step, 1 / sqrt(d^2 + E^2)
+// with two.  Branch-free.
 __device__ inline void jacobi_rot(double haa, double hcc, double hac, double thr, double negl2, double& c, double& s) {
   const bool active = hac * hac > thr * thr * fmax(haa, negl2) * fmax(hcc, negl2);
   const double D = hcc - haa, E = 2.0 * hac;
   const double q = D * D + E * E;
   double y = __builtin_amdgcn_rsq(q);
   y = y * (1.5 - 0.5 * q * y * y);
-  const double den = fabs(D) + q * y;   // |D| + sqrt(q)
-  double inv = __builtin_amdgcn_rcp(den);
-  inv = inv * (2.0 - den * inv);
-  const double t = ((D >= 0.0) == (E >= 0.0) ? 1.0 : -1.0) * fabs(E) * inv;
-  const double x = 1.0 + t * t;
+  const double d = fabs(D) + q * y;   // |D| + r
+  const double x = d * d + E * E;
   double z = __builtin_amdgcn_rsq(x);
   z = z * (1.5 - 0.5 * x * z * z);
   z = z * (1.5 - 0.5 * x * z * z);
-  c = active ? z : 1.0;
-  s = active ? z * t : 0.0;
+  const double sg = ((D >= 0.0) == (E >= 0.0)) ? fabs(E) : -fabs(E);
+  c = active ? d * z : 1.0;
+  s = active ? sg * z : 0.0;
 }
 
-// One workgroup (four wavefronts) per block pair.  Sums the Gram partials,
-// tests the pair and, unless it is converged, diagonalises the 32 x 32 Gram
-// matrix H by cyclic two-sided Jacobi in LDS: in each inner round the 32
-// indices form 16 disjoint pairs; thread (p, q) owns the 2 x 2 blocks of H
-// and of W (the accumulated rotations) at row pair p and column pair q,
-// computes both rotations itself and forms J_p^T H J_q and W J_q in
-// registers: one barrier after all reads, one after all writes.
-__global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_all, int nchunk, int m, int np,
-                                                           int round, double tol, double* off_all, long sOff,
-                                                           double* W_all, int* rot_all, const int* done,
-                                                           int inner_sweeps, const double* fro2_all,
-                                                           unsigned long long* entries) {
-  const int b = blockIdx.y;
+// One workgroup of eight wavefronts per block pair: the 32 x 32 Gram matrix
+// of the pair's columns, its convergence test and, unless the pair is
+// converged, its diagonalisation by cyclic two-sided Jacobi, giving the
+// rotation W.  Fused so that the Gram matrix never leaves the chip.
+//
+// Gram: wave w takes entries [512 k + 64 w, +64) of the column length in
+// slice k (the same number of slices in every wave); the 64 x 32 block is
+// loaded in one go (the next slice's loads are issued before the current one
+// is multiplied), staged through LDS two 16-entry subs at a time into the
+// operand layout of v_mfma_f64_16x16x4 (A lane l holds A[l%16][l/16], B lane
+// l holds B[l/16][l%16], D lane l register r holds D[4r + l/16][l%16]), and
+// accumulated per wave; the eight wave partials are summed in a fixed order.
+//
+// Eigensolve: in each inner round the 32 indices form 16 disjoint pairs;
+// thread (p, q) < 256 owns the 2 x 2 blocks of H and of W (the accumulated
+// rotations) at row pair p and column pair q, applies both rotations and
+// forms J_p^T H J_q and W J_q in registers; H is double-buffered, so one
+// barrier per inner round.  Threads 256..511 take part in the barriers only.
+static constexpr int JPT = 512;                 // threads of the pair kernel
+static constexpr int JSL = 64 * (JPT / 64);     // column-length entries per slice
+
+__device__ inline void gram_load(const double* Gp, const double* Gq, int m, int c0, int l, double (&v)[4][8]) {
+#pragma unroll
+  for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int c = c0 + sub * 16 + (l & 15), cc = min(c, m - 1);
+      const double x = (i < 4) ? Gp[(long)(i * 4) * m + cc] : Gq[(long)((i - 4) * 4) * m + cc];
+      v[sub][i] = (c < m) ? x : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(JPT) void jacobi_pair_kernel(const double* Gt_all, int m, int np, int round, long sG,
+                                                          double tol, double* off_all, long sOff, double* W_all,
+                                                          int* rot_all, const int* done, int inner_sweeps,
+                                                          const double* fro2_all, unsigned long long* entries) {
+  const int b = blockIdx.y, pr = blockIdx.x;
   const int nb = np / JW, pairs = nb / 2;
-  const int pr = blockIdx.x;
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
   int* rot = rot_all + (long)b * pairs + pr;
   if (done[b]) {
     if (tid == 0) *rot = 0;
     return;
   }
-  double* offv = off_all + b * sOff;
-  const double negl2 = 1e-26 * fro2_all[b];   // f^2 = (1e-13 |M|_F)^2
-  __shared__ double H2[2][JP][JP + 1];
-  __shared__ double W[JP][JP + 1];
-  __shared__ double wmax[4];
-  double (*H)[JP + 1] = H2[0];
-  __shared__ int any;
-  const double* part = part_all + ((long)b * pairs + pr) * nchunk * 1024;
-  {
-    // entries e = tid + 256 i, summed over the chunks in order with four
-    // chunks' loads in flight
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c0 = 0; c0 < nchunk; c0 += 4) {
-      double v[4][4];
+  int p, q;
+  circle_pair(nb, round, pr, p, q);
+  // staging [wave][2 subs][32][17]; then the wave partials [8][768]; then
+  // W [32][33] at the start and H (two copies of [32][33]) after the partials
+  __shared__ double sm[8 * 2 * JP * 17];
+  __shared__ double wmax[8];
+  // ---- Gram matrix ----
+  const double* Gt = Gt_all + b * sG;
+  const double* Gp = Gt + (long)(p * JW + (l >> 4)) * m;   // column i < JW of the pair: row p*JW + i
+  const double* Gq = Gt + (long)(q * JW + (l >> 4)) * m;   // column JW + i: row q*JW + i
+  d4v acc00 = d4v{0, 0, 0, 0}, acc01 = d4v{0, 0, 0, 0}, acc11 = d4v{0, 0, 0, 0};
+  const int nsl = (m + JSL - 1) / JSL;
+  double v[4][8], vn[4][8];
+  gram_load(Gp, Gq, m, wv * 64, l, v);
+  double* stg = sm + wv * 2 * JP * 17;
+  for (int k = 0; k < nsl; ++k) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+    for (int half = 0; half < 2; ++half) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          v[q][i] = (c0 + q < nchunk && i != 2) ? part[(long)(c0 + q) * 1024 + tid + 256 * i] : 0.0;
+      for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+        for (int i = 0; i < 8; ++i) stg[(s2 * JP + i * 4 + (l >> 4)) * 17 + (l & 15)] = v[2 * half + s2][i];
+      __syncthreads();
+      if (half == 0 && k + 1 < nsl) gram_load(Gp, Gq, m, (k + 1) * JSL + wv * 64, l, vn);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (c0 + q < nchunk) acc[i] += v[q][i];
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const double* buf = stg + s2 * JP * 17;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int kc = kk * 4 + (l >> 4);
+          const double a0 = buf[(l & 15) * 17 + kc], a1 = buf[(16 + (l & 15)) * 17 + kc];
+          acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc00, 0, 0, 0);
+          acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, acc01, 0, 0, 0);
+          acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc11, 0, 0, 0);
+        }
+      }
+      __syncthreads();
     }
+    if (k + 1 < nsl) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (i == 2) continue;   // tile (1, 0): the transpose of tile (0, 1), filled below
-      const int e = tid + 256 * i;
-      const int lane = e & 63, r = (e >> 6) & 3, tt = e >> 8, ti = tt >> 1, tj = tt & 1;
-      H[ti * 16 + 4 * r + (lane >> 4)][tj * 16 + (lane & 15)] = acc[i];
+      for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[sub][i] = vn[sub][i];
     }
   }
+  // wave partials of the tiles (0,0), (0,1), (1,1); the tile (1,0) is the
+  // transpose of (0,1) and is not formed
+  double* wp = sm + wv * 768;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    wp[(0 * 4 + r) * 64 + l] = acc00[r];
+    wp[(1 * 4 + r) * 64 + l] = acc01[r];
+    wp[(2 * 4 + r) * 64 + l] = acc11[r];
+  }
   __syncthreads();
-  {
+  double (*H2)[JP][JP + 1] = reinterpret_cast<double (*)[JP][JP + 1]>(sm + 8 * 768);
+  double (*W)[JP + 1] = reinterpret_cast<double (*)[JP + 1]>(sm);
+  double (*H)[JP + 1] = H2[0];
+  for (int e = tid; e < 768; e += JPT) {
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) a += sm[w * 768 + e];
+    const int lane = e & 63, r = (e >> 6) & 3, tt = e >> 8;
+    const int ti = tt == 2 ? 1 : 0, tj = tt == 0 ? 0 : 1;
+    H[ti * 16 + 4 * r + (lane >> 4)][tj * 16 + (lane & 15)] = a;
+  }
+  __syncthreads();
+  if (tid < 256) {
     const int i = tid >> 4, j = tid & 15;
     H[16 + j][i] = H[i][16 + j];
   }
-  for (int e = tid; e < JP * JP; e += 256) W[e / JP][e % JP] = (e / JP == e % JP) ? 1.0 : 0.0;
+  for (int e = tid; e < JP * JP; e += JPT) W[e / JP][e % JP] = (e / JP == e % JP) ? 1.0 : 0.0;
   __syncthreads();
 
   // ---- convergence measure of this pair (NaN-propagating max); the
   // hardware reciprocal square root is ample for a threshold test ----
+  double* offv = off_all + b * sOff;
+  const double negl2 = 1e-26 * fro2_all[b];   // f^2 = (1e-13 |M|_F)^2
   double om = 0.0;
-  for (int e = tid; e < JP * JP; e += 256) {
+  for (int e = tid; e < JP * JP; e += JPT) {
     const int i = e / JP, j = e % JP;
     if (j > i) {
       const double hii = fmax(H[i][i], negl2), hjj = fmax(H[j][j], negl2);
-      double v = fabs(H[i][j]) * __builtin_amdgcn_rsq(hii * hjj);
-      if (H[i][j] != H[i][j] || H[i][i] != H[i][i] || H[j][j] != H[j][j]) v = NAN;
-      om = (v != v || om != om) ? NAN : fmax(om, v);
+      double x = fabs(H[i][j]) * __builtin_amdgcn_rsq(hii * hjj);
+      if (H[i][j] != H[i][j] || H[i][i] != H[i][i] || H[j][j] != H[j][j]) x = NAN;
+      om = (x != x || om != om) ? NAN : fmax(om, x);
     }
   }
   for (int w = 32; w > 0; w >>= 1) {
@@ -307,7 +297,7 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
   __syncthreads();
   {
     double a = wmax[0];
-    for (int k = 1; k < 4; ++k) a = (a != a || wmax[k] != wmax[k]) ? NAN : fmax(a, wmax[k]);
+    for (int k = 1; k < JPT / 64; ++k) a = (a != a || wmax[k] != wmax[k]) ? NAN : fmax(a, wmax[k]);
     om = a;
   }
   if (tid == 0) {
@@ -318,60 +308,60 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(const double* part_al
   }
   if (!(om > tol)) return;   // converged pair (or NaN: leave the data as is)
 
-  // H is double-buffered: round rr reads one copy and writes the other (the
-  // 2 x 2 blocks of all threads cover H), so one barrier per round suffices;
-  // W entries are read and written by their owner only within a round.
   // Thread (pp, qq) computes the rotation of index pair qq and takes that of
-  // pair pp from the lane of its wavefront that computed it.  The pairs of
-  // the circle tournament advance by one position per round.
+  // pair pp from the lane of its wavefront that computed it (computing both
+  // in every thread doubles the quarter-rate reciprocal square roots and is
+  // slower).  The pairs of the circle tournament advance by one position per
+  // round; the 2 x 2 blocks of the 256 owners cover H, and W entries are read
+  // and written by their owner only within a round.
+  const bool owner = tid < 256;
   const double thr = 0.1 * tol;
-  const int pp = tid >> 4, qq = tid & 15;
+  const int pp = (tid >> 4) & 15, qq = tid & 15;
   const int src = (l & 48) | pp;   // lane (pp mod 4, pp) of this wavefront
   int cur = 0;
   for (int sw = 0; sw < inner_sweeps; ++sw) {
-    if (tid == 0) any = 0;
-    __syncthreads();
     int ap, cp, aq, cq;
     circle_pair(JP, 0, pp, ap, cp);
     circle_pair(JP, 0, qq, aq, cq);
+    int moved = 0;
     for (int rr = 0; rr < JP - 1; ++rr) {
-      double (*Hc)[JP + 1] = H2[cur];
-      double (*Hn)[JP + 1] = H2[cur ^ 1];
-      double c2, s2;
-      jacobi_rot(Hc[aq][aq], Hc[cq][cq], Hc[aq][cq], thr, negl2, c2, s2);
-      const double c1 = __shfl(c2, src), s1 = __shfl(s2, src);
-      if (s2 != 0.0) any = 1;
-      const double h00 = Hc[ap][aq], h01 = Hc[ap][cq], h10 = Hc[cp][aq], h11 = Hc[cp][cq];
-      const double w00 = W[ap][aq], w01 = W[ap][cq], w10 = W[cp][aq], w11 = W[cp][cq];
-      const double r00 = c1 * h00 - s1 * h10, r01 = c1 * h01 - s1 * h11;
-      const double r10 = s1 * h00 + c1 * h10, r11 = s1 * h01 + c1 * h11;
-      Hn[ap][aq] = c2 * r00 - s2 * r01;
-      Hn[ap][cq] = s2 * r00 + c2 * r01;
-      Hn[cp][aq] = c2 * r10 - s2 * r11;
-      Hn[cp][cq] = s2 * r10 + c2 * r11;
-      W[ap][aq] = c2 * w00 - s2 * w01;
-      W[ap][cq] = s2 * w00 + c2 * w01;
-      W[cp][aq] = c2 * w10 - s2 * w11;
-      W[cp][cq] = s2 * w10 + c2 * w11;
+      if (owner) {
+        double (*Hc)[JP + 1] = H2[cur];
+        double (*Hn)[JP + 1] = H2[cur ^ 1];
+        // every LDS read of the round first: the reads of the 2 x 2 blocks
+        // overlap the rotation's dependent chain
+        const double haa = Hc[aq][aq], hcc = Hc[cq][cq], hac = Hc[aq][cq];
+        const double h00 = Hc[ap][aq], h01 = Hc[ap][cq], h10 = Hc[cp][aq], h11 = Hc[cp][cq];
+        const double w00 = W[ap][aq], w01 = W[ap][cq], w10 = W[cp][aq], w11 = W[cp][cq];
+        double c2, s2;
+        jacobi_rot(haa, hcc, hac, thr, negl2, c2, s2);
+        const double c1 = __shfl(c2, src), s1 = __shfl(s2, src);
+        moved |= (s2 != 0.0) ? 1 : 0;
+        const double r00 = c1 * h00 - s1 * h10, r01 = c1 * h01 - s1 * h11;
+        const double r10 = s1 * h00 + c1 * h10, r11 = s1 * h01 + c1 * h11;
+        Hn[ap][aq] = c2 * r00 - s2 * r01;
+        Hn[ap][cq] = s2 * r00 + c2 * r01;
+        Hn[cp][aq] = c2 * r10 - s2 * r11;
+        Hn[cp][cq] = s2 * r10 + c2 * r11;
+        W[ap][aq] = c2 * w00 - s2 * w01;
+        W[ap][cq] = s2 * w00 + c2 * w01;
+        W[cp][aq] = c2 * w10 - s2 * w11;
+        W[cp][cq] = s2 * w10 + c2 * w11;
+      }
       cur ^= 1;
       // next round of the circle: index 0 keeps player 0, the others move on
-      if (pp == 0) ++cp;
-      else {
-        ap = (ap == JP - 1) ? 1 : ap + 1;
-        cp = (cp == JP - 1) ? 1 : cp + 1;
-      }
-      if (qq == 0) ++cq;
-      else {
-        aq = (aq == JP - 1) ? 1 : aq + 1;
-        cq = (cq == JP - 1) ? 1 : cq + 1;
-      }
+      const int ap1 = (ap == JP - 1) ? 1 : ap + 1, cp1 = (cp == JP - 1) ? 1 : cp + 1;
+      const int aq1 = (aq == JP - 1) ? 1 : aq + 1, cq1 = (cq == JP - 1) ? 1 : cq + 1;
+      ap = (pp == 0) ? ap : ap1;
+      cp = (pp == 0) ? cp + 1 : cp1;
+      aq = (qq == 0) ? aq : aq1;
+      cq = (qq == 0) ? cq + 1 : cq1;
       __syncthreads();
     }
-    if (!any) break;
-    __syncthreads();
+    if (!__syncthreads_or(moved)) break;
   }
   double* Wout = W_all + ((long)b * pairs + pr) * JP * JP;
-  for (int e = tid; e < JP * JP; e += 256) Wout[e] = W[e / JP][e % JP];
+  for (int e = tid; e < JP * JP; e += JPT) Wout[e] = W[e / JP][e % JP];
 }
 
 // new columns = old columns W for the rows of Gt (chunks 0 .. nchG-1 of JCHR
@@ -390,48 +380,55 @@ __global__ __launch_bounds__(512) void jacobi_rotate_kernel(double* Gt_all, doub
   int p, q;
   circle_pair(nb, round, pr, p, q);
   __shared__ double Ws[JP][JP + 1];
-  __shared__ int rowidx[JP];
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
-  const double* Wg = W_all + ((long)b * pairs + pr) * JP * JP;
-  for (int e = tid; e < JP * JP; e += 512) Ws[e / JP][e % JP] = Wg[e];
-  if (tid < JP) rowidx[tid] = (tid < JW) ? p * JW + tid : q * JW + (tid - JW);
-  __syncthreads();
   const bool isG = (int)blockIdx.y < nchG;
   double* X = isG ? Gt_all + b * sG : Vt_all + b * sV;
   const int len = isG ? m : np;
   const int c0 = (isG ? blockIdx.y : blockIdx.y - nchG) * JCHR + wv * 64;
-  if (c0 >= len) return;   // whole wave past the end (no barrier follows)
-  // the wave's 64 entries of all 32 columns are loaded before any is written
+  // the wave's 64 entries of all 32 columns are loaded before any is written,
+  // and before W (their latency covers W's); column i of the pair is row
+  // p*JW + i (i < JW) or q*JW + i - JW of X.  Entries past the end read the
+  // last one (in bounds, never stored), so the loads carry no branches.
+  double* Xp = X + (long)(p * JW + (l >> 4)) * len;
+  double* Xq = X + (long)(q * JW + (l >> 4)) * len;
   double old[4][8];
 #pragma unroll
   for (int tc = 0; tc < 4; ++tc) {
-    const int c = c0 + tc * 16 + (l & 15);
+    const int c = min(c0 + tc * 16 + (l & 15), len - 1);
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) old[tc][kk] = (c < len) ? X[(long)rowidx[kk * 4 + (l >> 4)] * len + c] : 0.0;
+    for (int kk = 0; kk < 8; ++kk)
+      old[tc][kk] = (kk < 4) ? Xp[(long)(kk * 4) * len + c] : Xq[(long)((kk - 4) * 4) * len + c];
+    // loads stay in column-tile order: the multiply of tile 0 waits for its
+    // eight loads only
+    __builtin_amdgcn_sched_barrier(0);
   }
-  // eight independent accumulator chains (4 column tiles x 2 row tiles), interleaved
-  d4v d[4][2];
-#pragma unroll
-  for (int tc = 0; tc < 4; ++tc)
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti) d[tc][ti] = d4v{0, 0, 0, 0};
+  const double* Wg = W_all + ((long)b * pairs + pr) * JP * JP;
+  for (int e = tid; e < JP * JP; e += 512) Ws[e / JP][e % JP] = Wg[e];
+  __syncthreads();
+  if (c0 >= len) return;   // whole wave past the end (no barrier follows)
+  // column tile by column tile (two independent accumulator chains each), so
+  // that the stores of one tile stream out while the next is multiplied
+  double a[8][2];
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk) {
-    const double a0 = Ws[kk * 4 + (l >> 4)][l & 15], a1 = Ws[kk * 4 + (l >> 4)][16 + (l & 15)];   // (W^T)[i][j]
-#pragma unroll
-    for (int tc = 0; tc < 4; ++tc) {
-      d[tc][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, old[tc][kk], d[tc][0], 0, 0, 0);
-      d[tc][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, old[tc][kk], d[tc][1], 0, 0, 0);
-    }
+    a[kk][0] = Ws[kk * 4 + (l >> 4)][l & 15];        // (W^T)[i][j]
+    a[kk][1] = Ws[kk * 4 + (l >> 4)][16 + (l & 15)];
   }
 #pragma unroll
   for (int tc = 0; tc < 4; ++tc) {
+    d4v d0 = d4v{0, 0, 0, 0}, d1 = d4v{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk][0], old[tc][kk], d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk][1], old[tc][kk], d1, 0, 0, 0);
+    }
     const int c = c0 + tc * 16 + (l & 15);
     if (c < len) {
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) X[(long)rowidx[ti * 16 + 4 * r + (l >> 4)] * len + c] = d[tc][ti][r];
+      for (int r = 0; r < 4; ++r) {
+        Xp[(long)(4 * r) * len + c] = d0[r];
+        Xq[(long)(4 * r) * len + c] = d1[r];
+      }
     }
   }
 }
@@ -608,13 +605,10 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
     // algorithmic work of one round for the batch entries still running (the
     // rotation's share is added from the device counter after the sweep)
     const double gram_fl = (double)L.pairs * running * 2.0 * JP * JP * n;
-    const double gram_by = (double)L.pairs * running * 8.0 * (JP * (double)n + 1024.0 * L.nchG);
-    const double solve_by = (double)L.pairs * running * 8.0 * 1024.0 * (L.nchG + 1);
+    const double gram_by = (double)L.pairs * running * 8.0 * (JP * (double)n + JP * JP);
     for (int r = 0; r < L.rounds; ++r) {
-      launch_timed(KC_JACOBI_GRAM, gram_fl, gram_by, jacobi_gram_kernel, dim3(L.pairs, L.nchG, batch), dim3(256), 0,
-                   s, (const double*)Gt, n, L.np, r, L.sG, part, L.nchG, (const int*)done);
-      launch_timed(KC_JACOBI_SOLVE, 0.0, solve_by, jacobi_solve_kernel, dim3(L.pairs, batch), dim3(256), 0, s,
-                   (const double*)part, L.nchG, n, L.np, r, tol, off, L.sOff, Wr, rot, (const int*)done, inner,
+      launch_timed(KC_JACOBI_GRAM, gram_fl, gram_by, jacobi_pair_kernel, dim3(L.pairs, batch), dim3(JPT), 0, s,
+                   (const double*)Gt, n, L.np, r, L.sG, tol, off, L.sOff, Wr, rot, (const int*)done, inner,
                    (const double*)fro2, cnt);
       launch_timed(KC_JACOBI_ROTATE, 0.0, 0.0, jacobi_rotate_kernel, dim3(L.pairs, nrG + nrV, batch), dim3(512), 0, s,
                    Gt, Vt, n, L.np, r, L.sG, L.sV, (const double*)Wr, (const int*)rot, nrG, (const int*)done);

@@ -20,8 +20,8 @@ enum KernelClass : int {
   KC_GEMM_F64 = 0,
   KC_GEMM_F32 = 1,
   KC_GEMM_BF16X3 = 2,
-  KC_JACOBI_GRAM = 3,
-  KC_JACOBI_SOLVE = 4,
+  KC_JACOBI_GRAM = 3,    // pair kernel: Gram matrix + 32 x 32 eigensolve
+  KC_JACOBI_SOLVE = 4,   // unused (the eigensolve runs in the pair kernel)
   KC_JACOBI_ROTATE = 5,
   KC_GEMM_BF16X6 = 6,
   KC_COUNT = 7

@@ -323,7 +323,7 @@ def test_kernel_timing_sampling():
         obj.sweep(3)
         res[stride] = obj.kernel_timing()
         obj.kernel_timing_enable(False)
-    for k in ("gemm_fp64", "jacobi_gram", "jacobi_solve", "jacobi_rotate"):
+    for k in ("gemm_fp64", "jacobi_pair", "jacobi_rotate"):
         ms1, n1, f1, b1 = res[1][k]
         ms4, n4, f4, b4 = res[4][k]
         assert n1 == n4 > 0 and f1 == f4 and b1 == b4, k
