@@ -135,8 +135,11 @@ ctm_status ctm_last_stats(ctm_ctx* ctx, double* gemm_flops, double* svd_sweeps);
  * checks.  ctm_debug_gemm: C[M][N] = op(A) op(B), row-major, prec CTM_FP64
  * (double) or CTM_FP32 / CTM_BF16X3 / CTM_BF16X6 (float); transA: A stored K x M, transB: B
  * stored N x K.  work: NULL, or device scratch of ctm_debug_gemm_work_bytes
- * bytes; when that size is nonzero (long K, few 64 x 64 output tiles) the
- * product runs split over K, as the contractions of the library do.
+ * bytes; when that size is nonzero the product runs as the contractions of
+ * the library run it: split over K (long K, few 64 x 64 output tiles), or,
+ * for BF16X3 products of 2^31 multiply-adds or more with both output
+ * dimensions >= 1024, on operands split once into k-contiguous bf16 planes
+ * (128 x 128 tiles, K sliced when the tiles are few).
  * ctm_debug_svd: batch n x n FP64 matrices M (row-major, consecutive) ->
  * U S V^T, S descending; work = ctm_debug_svd_work_bytes bytes of device
  * memory; *sweeps in: sweep cap (<= 0: 60), out: sweeps run.  Both

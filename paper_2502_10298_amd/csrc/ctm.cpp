@@ -1132,6 +1132,10 @@ ctm_status ctm_env_import(ctm_ctx* c, const double* env_dev) {
 }
 
 size_t ctm_debug_gemm_work_bytes(int prec, int M, int N, int K) {
+  if (prec == CTM_BF16X3 && M > 0 && N > 0 && K > 0) {
+    const size_t bb = bf16x3_big_scratch_bytes(M, N, K);
+    if (bb) return bb;
+  }
   return (size_t)splitk_scratch_elems(M, N, K) * (prec == CTM_FP64 ? 8 : 4);
 }
 
@@ -1142,6 +1146,12 @@ ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K,
   const long lda = transA ? M : K, ldb = transB ? K : N;
   const bool split = work && splitk_scratch_elems(M, N, K) > 0;
   hipError_t e;
+  if (prec == CTM_BF16X3 && work && M > 0 && N > 0 && bf16x3_big_scratch_bytes(M, N, K) > 0) {
+    e = gemm_bf16x3_big(s, transA, transB, M, N, K, 1.f, (const float*)A, lda, (const float*)B, ldb, 0.f, (float*)C,
+                        N, work);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? CTM_OK : CTM_EDEVICE;
+  }
   if (prec == CTM_FP64)
     e = split ? gemm_f64_splitk(s, transA, transB, M, N, K, 1.0, (const double*)A, lda, (const double*)B, ldb, 0.0,
                                 (double*)C, N, (double*)work)

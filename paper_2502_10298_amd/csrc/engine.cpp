@@ -218,6 +218,20 @@ Ten Engine::normalize(const Ten& A) {
 void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten& A, long offA, long lda,
                   const Ten& B, long offB, long ldb, double beta, const Ten& C, long offC, long ldc) {
   flops_gemm += 2L * M * N * K;
+  // large BF16X3 products: operands split once into bf16 planes (scratch from the arena)
+  if (C.dt == F32 && prec == Prec::BF16X3) {
+    const size_t bb = bf16x3_big_scratch_bytes(M, N, K);
+    if (bb > 0) {
+      size_t mk = ar.mark();
+      void* w = ar.alloc(bb);
+      if (!dry && ok() && w)
+        check(gemm_bf16x3_big(s, tA, tB, M, N, K, (float)alpha, A.f32() + offA, lda, B.f32() + offB, ldb,
+                              (float)beta, C.f32() + offC, ldc, w));
+      if (!w && !dry) status = 2;   // workspace exhausted
+      ar.release(mk);
+      return;
+    }
+  }
   // Split-K (long K, few output tiles): the scratch for the slices comes from the arena
   const long sk = splitk_scratch_elems(M, N, K);
   if (sk > 0) {

@@ -414,4 +414,231 @@ hipError_t gemm_f32_splitk(hipStream_t s, Prec mode, bool tA, bool tB, int M, in
       [&](int nsl) { return splitk_reduce_f32(s, scratch, nsl, M, N, alpha, beta, C, ldc); });
 }
 
+// ---------------------------------------------------------------------------
+// Large BF16X3 products.  The operands are split once into bf16 hi / lo
+// planes stored k-contiguous (A' = op(A) as M x K, B' = op(B)^T as N x K,
+// zero-padded to 128 rows and 64 k), and one bf16 GEMM runs over the
+// concatenation
+//   C = [A_hi | A_hi | A_lo] [B_hi | B_lo | B_hi]^T,
+// i.e. the same three products as the in-LDS split.  128 x 128 output tiles
+// per workgroup (2 x 2 waves of 64 x 64 = 4 x 4 MFMA 16x16x32 tiles), BK =
+// 64, both operand tiles k-contiguous in LDS so that every MFMA operand is
+// one 16-byte read, LDS double-buffered (one barrier per k step) with the
+// next step's 16-byte global loads in flight during the MFMAs.  When the
+// output has too few tiles to fill the chip, the concatenated K runs in
+// slices into partial products that one more pass adds in order.
+// ---------------------------------------------------------------------------
+static constexpr int XBM = 128, XBK = 64, XPAD = 8;
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// H, L [Rp][Kp] = hi / lo split of X (rows R, k extent K); TRANS: X stored
+// K x R (element (r, k) at X[k ld + r]), else R x K.  Grid (Kp / 64, Rp / 64):
+// a 64 x 64 tile is read along X's contiguous dimension into LDS, then every
+// thread splits eight consecutive k of one row and writes them as one
+// 16-byte vector per plane.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void bf16_split_kernel(const float* __restrict__ X, long ld, int R, int K, int Kp,
+                                                         __bf16* __restrict__ H, __bf16* __restrict__ L) {
+  __shared__ float tile[64][65];   // [r][k]
+  const int r0 = blockIdx.y * 64, k0 = blockIdx.x * 64, t = threadIdx.x;
+  // all sixteen loads in flight before the first LDS write; out-of-range
+  // entries read an in-range one (clamped, no branch) and count as zero
+  float v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int a = (t >> 6) + 4 * i, c = t & 63;   // a: slow index, c: along X's contiguous dimension
+    const int r = TRANS ? r0 + c : r0 + a, k = TRANS ? k0 + a : k0 + c;
+    const long rc = min(r, R - 1), kc = min(k, K - 1);
+    const float x = TRANS ? X[kc * ld + rc] : X[rc * ld + kc];
+    v[i] = (r < R && k < K) ? x : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int a = (t >> 6) + 4 * i, c = t & 63;
+    if (TRANS)
+      tile[c][a] = v[i];
+    else
+      tile[a][c] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = t + 256 * j, rr = q >> 3, kc = (q & 7) * 8;
+    bf8 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 sp[2];
+      split_bf16<2>(tile[rr][kc + e], sp);
+      hi[e] = sp[0];
+      lo[e] = sp[1];
+    }
+    const long o = (long)(r0 + rr) * Kp + k0 + kc;
+    *reinterpret_cast<bf8*>(H + o) = hi;
+    *reinterpret_cast<bf8*>(L + o) = lo;
+  }
+}
+
+// Slice z of the concatenated K' = 3 Kp covers [z ksl, min(3 Kp, (z+1) ksl));
+// P == nullptr: C = alpha acc + beta C, else P[z] = acc (M x N).
+__global__ __launch_bounds__(256) void gemm_bf16nt_kernel(int M, int N, int Kp, int ksl, float alpha,
+                                                          const __bf16* __restrict__ Ah,
+                                                          const __bf16* __restrict__ Al,
+                                                          const __bf16* __restrict__ Bh,
+                                                          const __bf16* __restrict__ Bl, float beta,
+                                                          float* __restrict__ C, long ldc, float* __restrict__ P) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][XBM][XBK + XPAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][XBM][XBK + XPAD];
+  const int bm = blockIdx.y * XBM, bn = blockIdx.x * XBM, z = blockIdx.z;
+  const int k_lo = z * ksl, k_hi = min(3 * Kp, k_lo + ksl);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+  // loader: 16-byte chunk c = tid + 256 i of a 128 x 64 tile: row c / 8, k 8 (c % 8)
+  u4v ra[4], rb[4];
+  auto load = [&](int kp) {
+    const int g = kp / Kp, k = kp - g * Kp;
+    const __bf16* A = (g == 2) ? Al : Ah;
+    const __bf16* B = (g == 1) ? Bl : Bh;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = tid + 256 * i, row = c >> 3, kc = (c & 7) * 8;
+      ra[i] = *reinterpret_cast<const u4v*>(A + (long)(bm + row) * Kp + k + kc);
+      rb[i] = *reinterpret_cast<const u4v*>(B + (long)(bn + row) * Kp + k + kc);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = tid + 256 * i, row = c >> 3, kc = (c & 7) * 8;
+      *reinterpret_cast<u4v*>(&As[buf][row][kc]) = ra[i];
+      *reinterpret_cast<u4v*>(&Bs[buf][row][kc]) = rb[i];
+    }
+  };
+  load(k_lo);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int kp = k_lo; kp < k_hi; kp += XBK) {
+    const bool more = kp + XBK < k_hi;
+    if (more) load(kp + XBK);
+#pragma unroll
+    for (int ks = 0; ks < XBK / 32; ++ks) {
+      const int kq = ks * 32 + 8 * (lane >> 4);
+      bf8 a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = *reinterpret_cast<const bf8*>(&As[buf][wm * 64 + t * 16 + (lane & 15)][kq]);
+        b[t] = *reinterpret_cast<const bf8*>(&Bs[buf][wn * 64 + t * 16 + (lane & 15)][kq]);
+      }
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = bm + wm * 64 + ti * 16 + 4 * (lane >> 4) + r;
+        const int n = bn + wn * 64 + tj * 16 + (lane & 15);
+        if (m < M && n < N) {
+          if (P) {
+            P[(long)z * M * N + (long)m * N + n] = acc[ti][tj][r];
+          } else {
+            const float v = alpha * acc[ti][tj][r];
+            const long o = (long)m * ldc + n;
+            C[o] = (beta == 0.f) ? v : v + beta * C[o];
+          }
+        }
+      }
+}
+
+struct Bf16BigPlan {
+  int Mp = 0, Np = 0, Kp = 0, S = 0, ksl = 0;
+  size_t offAh = 0, offAl = 0, offBh = 0, offBl = 0, offP = 0, total = 0;
+};
+
+// The pre-split path pays for itself (measured on gfx950: 1.36x at 1024 x
+// 1024 x 2048, 1.9x at 4096^3, slower than the in-LDS split for thin outputs
+// such as 8192 x 128 x 1024) from 2^31 multiply-adds with both output
+// dimensions >= 1024; slices give the chip about 256 workgroups, each with
+// at least eight k steps, within 64 MiB of partials.
+static bool bf16_big_plan(int M, int N, int K, Bf16BigPlan& p) {
+  if (M < 1024 || N < 1024 || K < 256 || (double)M * N * (double)K < 2147483648.0) return false;
+  p.Mp = (M + XBM - 1) / XBM * XBM;
+  p.Np = (N + XBM - 1) / XBM * XBM;
+  p.Kp = (K + XBK - 1) / XBK * XBK;
+  const long tiles = (long)(p.Mp / XBM) * (p.Np / XBM);
+  const int ksteps = 3 * p.Kp / XBK;
+  int S = 1;
+  if (tiles < 256) S = (int)std::min<long>((256 + tiles - 1) / tiles, ksteps / 8);
+  while (S > 1 && (long)S * M * N * 4 > (64L << 20)) --S;
+  if (S < 1) S = 1;
+  const int per = (ksteps + S - 1) / S;
+  p.ksl = per * XBK;
+  p.S = (ksteps + per - 1) / per;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t ap = sizeof(__bf16) * (size_t)p.Mp * p.Kp, bp = sizeof(__bf16) * (size_t)p.Np * p.Kp;
+  p.offAh = take(ap);
+  p.offAl = take(ap);
+  p.offBh = take(bp);
+  p.offBl = take(bp);
+  p.offP = take(p.S > 1 ? sizeof(float) * (size_t)p.S * M * N : 0);
+  p.total = off;
+  return true;
+}
+
+size_t bf16x3_big_scratch_bytes(int M, int N, int K) {
+  Bf16BigPlan p;
+  return bf16_big_plan(M, N, K, p) ? p.total : 0;
+}
+
+hipError_t gemm_bf16x3_big(hipStream_t s, bool tA, bool tB, int M, int N, int K, float alpha, const float* A,
+                           long lda, const float* B, long ldb, float beta, float* C, long ldc, void* scratch) {
+  Bf16BigPlan p;
+  if (!bf16_big_plan(M, N, K, p) || !scratch) return hipErrorInvalidValue;
+  char* w = (char*)scratch;
+  __bf16 *Ah = (__bf16*)(w + p.offAh), *Al = (__bf16*)(w + p.offAl);
+  __bf16 *Bh = (__bf16*)(w + p.offBh), *Bl = (__bf16*)(w + p.offBl);
+  float* P = p.S > 1 ? (float*)(w + p.offP) : nullptr;
+  const int kind = KC_GEMM_BF16X3;
+  // op(A) rows M: stored K x M when tA;  op(B)^T rows N: stored K x N unless tB
+  const double byA = 4.0 * M * K + 4.0 * p.Mp * p.Kp, byB = 4.0 * N * K + 4.0 * p.Np * p.Kp;
+  if (tA)
+    launch_timed(kind, 0.0, byA, bf16_split_kernel<true>, dim3(p.Kp / 64, p.Mp / 64), dim3(256), 0, s, A, lda, M, K,
+                 p.Kp, Ah, Al);
+  else
+    launch_timed(kind, 0.0, byA, bf16_split_kernel<false>, dim3(p.Kp / 64, p.Mp / 64), dim3(256), 0, s, A, lda, M,
+                 K, p.Kp, Ah, Al);
+  if (!tB)
+    launch_timed(kind, 0.0, byB, bf16_split_kernel<true>, dim3(p.Kp / 64, p.Np / 64), dim3(256), 0, s, B, ldb, N, K,
+                 p.Kp, Bh, Bl);
+  else
+    launch_timed(kind, 0.0, byB, bf16_split_kernel<false>, dim3(p.Kp / 64, p.Np / 64), dim3(256), 0, s, B, ldb, N,
+                 K, p.Kp, Bh, Bl);
+  const double fl = 2.0 * M * N * (double)K;
+  const double by = 2.0 * 2.0 * ((double)p.Mp + p.Np) * p.Kp + 4.0 * M * N * (beta != 0.f ? 2 : 1);
+  launch_timed(kind, fl, by, gemm_bf16nt_kernel, dim3(p.Np / XBM, p.Mp / XBM, p.S), dim3(256), 0, s, M, N, p.Kp,
+               p.ksl, alpha, (const __bf16*)Ah, (const __bf16*)Al, (const __bf16*)Bh, (const __bf16*)Bl, beta, C, ldc,
+               P);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && P) e = splitk_reduce_f32(s, P, p.S, M, N, alpha, beta, C, ldc);
+  return e;
+}
+
 }  // namespace sctm

@@ -50,6 +50,13 @@ hipError_t gemm_f64_splitk(hipStream_t s, bool tA, bool tB, int M, int N, int K,
 hipError_t gemm_f32_splitk(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, int K, float alpha,
                            const float* A, long lda, const float* B, long ldb, float beta, float* C, long ldc,
                            float* scratch);
+// Large BF16X3 products (both output dimensions >= 1024, 2^31 multiply-adds
+// or more): operands split once into k-contiguous bf16 planes,
+// 128 x 128 tiles; scratch = bf16x3_big_scratch_bytes(M, N, K) bytes, 0 when
+// the shape takes the plain kernel (gemm_bf16x3_big then fails).
+size_t bf16x3_big_scratch_bytes(int M, int N, int K);
+hipError_t gemm_bf16x3_big(hipStream_t s, bool tA, bool tB, int M, int N, int K, float alpha, const float* A,
+                           long lda, const float* B, long ldb, float beta, float* C, long ldc, void* scratch);
 hipError_t splitk_reduce_f64(hipStream_t s, const double* P, int S, int M, int N, double alpha, double beta, double* C,
                              long ldc);
 hipError_t splitk_reduce_f32(hipStream_t s, const float* P, int S, int M, int N, float alpha, float beta, float* C,

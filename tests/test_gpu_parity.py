@@ -61,6 +61,24 @@ def test_gemm_split_k(prec, tol, shape, tA, tB):
     assert err < tol, float(err)
 
 
+@pytest.mark.parametrize("shape", [(1030, 1100, 1900), (2100, 2200, 700), (1024, 1024, 2048), (1500, 4100, 2000)])
+@pytest.mark.parametrize("tA,tB", [(False, False), (True, False), (False, True), (True, True)])
+def test_gemm_bf16x3_presplit(shape, tA, tB):
+    """Large BF16X3 products run on operands split once into k-contiguous
+    bf16 planes (128 x 128 tiles; ragged M, N and K; K sliced when the tiles
+    are few): same bound as the in-LDS split against the FP64 product."""
+    M, N, K = shape
+    assert b.lib().ctm_debug_gemm_work_bytes(b.PREC["bf16x3"], M, N, K) > 0
+    _say("gemm bf16x3 presplit", shape, tA, tB)
+    g = torch.Generator(device="cpu").manual_seed(M * 3 + N)
+    A = torch.randn((K, M) if tA else (M, K), generator=g, dtype=torch.float64)
+    B = torch.randn((N, K) if tB else (K, N), generator=g, dtype=torch.float64)
+    ref = (A.T if tA else A) @ (B.T if tB else B)
+    C = b.debug_gemm(A.to(DEV, torch.float32), B.to(DEV, torch.float32), tA, tB, "bf16x3").double().cpu()
+    err = (C - ref).norm() / ref.norm()
+    assert err < 4e-5, float(err)
+
+
 @pytest.mark.parametrize("n,batch", [(5, 1), (33, 2), (100, 3), (257, 1), (1024, 2)])
 def test_jacobi_svd(n, batch):
     _say("svd", n, batch)
