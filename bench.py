@@ -78,6 +78,12 @@ def parse():
                     help="HIP events on every k-th launch of each kernel class in the timed steps")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device once (calibrates the HBM byte counters) and exit")
+    ap.add_argument("--scaling", type=str, default="",
+                    help="comma-separated bulk bond dimensions D: instead of the bench line, time sweeps of a 1x1 "
+                         "cell at fixed chi_E = chi_I for each D and fit time ~ D^a over D >= 6 (one JSON line)")
+    ap.add_argument("--scaling-chi", type=int, default=170)
+    ap.add_argument("--scaling-p", type=int, default=2)
+    ap.add_argument("--scaling-prec", default="bf16x3")
     return ap.parse_args()
 
 
@@ -131,6 +137,43 @@ def cpu_baseline(threads: int) -> dict:
                       f"{dt:.1f} s, scaled x{4 * w['Ly']} to one sweep"}
 
 
+def scaling(args) -> None:
+    """Time of one sweep (four directional moves, each absorbing the ket and
+    bra layers of every column) against the bulk bond dimension D at fixed
+    chi_E = chi_I, on seeded Gaussian 1x1 states.  Two untimed sweeps grow the
+    environment from the identity boundary to its full dimension first."""
+    import numpy as np
+    import torch
+    from paper_2502_10298_amd import binding as b
+    from paper_2502_10298_amd import inputs as inp
+    chi, p = args.scaling_chi, args.scaling_p
+    rows = []
+    for D in [int(x) for x in args.scaling.split(",") if x]:
+        A = torch.tensor(inp.peps_gaussian(700 + D, 1, 1, p, D), device="cuda:0")
+        obj = b.SplitCTM(A, chi, chi, prec=args.scaling_prec)
+        obj.sweep(2)
+        torch.cuda.synchronize()
+        n = 2
+        t0 = time.perf_counter()
+        obj.sweep(n)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        rows.append({"D": D, "s_per_sweep": dt, "s_per_move": dt / 4, "jacobi_sweeps_per_call": obj.stats()[1] / n})
+        say(f"D={D}: {dt:.3f} s per sweep")
+        obj.close()
+        del obj, A
+        torch.cuda.empty_cache()
+    pts = [(r["D"], r["s_per_sweep"]) for r in rows if r["D"] >= 6]
+    fit = None
+    if len(pts) >= 2:
+        x = np.log([d for d, _ in pts])
+        y = np.log([t for _, t in pts])
+        fit = float(np.polyfit(x, y, 1)[0])
+    print(json.dumps({"scaling": rows, "chi_E": chi, "chi_I": chi, "p": p, "cell": "1x1",
+                      "prec": args.scaling_prec, "state": "seeded Gaussian", "exponent_fit_D_ge_6": fit}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -146,6 +189,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.scaling:
+        scaling(args)
+        return
     if args.copy_probe:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
         y = torch.empty_like(x)

@@ -114,6 +114,14 @@ size_t ctm_projectors_elems(const ctm_config* cfg);
  * bond energies of each site. */
 ctm_status ctm_energy(ctm_ctx* ctx, const double* h_host, double* e_site, double* e_bonds);
 
+/* As ctm_energy with a different Hamiltonian on the horizontal bonds
+ * (h_host, s1 = left site) and on the vertical bonds (hv_host, s1 = upper
+ * site), same layout.  This is what a coarse-grained lattice needs, e.g. the
+ * honeycomb lattice with two sites per tensor (p = 4), where the two bond
+ * directions couple different sub-sites and an on-site term can be shared
+ * out over the four bonds of a site. */
+ctm_status ctm_energy_hv(ctm_ctx* ctx, const double* h_host, const double* hv_host, double* e_site, double* e_bonds);
+
 /* E(A) = energy after exactly n_sweeps sweeps from the start environment, and
  * dE/dA (device, FP64, layout of A) by reverse mode with the hand-written
  * adjoints; the environment is checkpointed every ckpt_every sweeps and the
@@ -121,6 +129,10 @@ ctm_status ctm_energy(ctm_ctx* ctx, const double* h_host, double* e_site, double
  * environment is left at the state after the n_sweeps sweeps. */
 ctm_status ctm_energy_grad(ctm_ctx* ctx, const double* h_host, int n_sweeps, int ckpt_every, double* e_site,
                            double* dA_dev);
+/* As ctm_energy_grad with separate horizontal (h_host) and vertical
+ * (hv_host) bond Hamiltonians, as in ctm_energy_hv. */
+ctm_status ctm_energy_grad_hv(ctm_ctx* ctx, const double* h_host, const double* hv_host, int n_sweeps,
+                              int ckpt_every, double* e_site, double* dA_dev);
 
 /* Current environment to / from a device FP64 buffer in the packed layout
  * (ctm_env_elems doubles).  Import also resets the start environment. */

@@ -17,22 +17,23 @@ from . import split_ctmrg as sc
 
 
 def energy_of(A_cell: torch.Tensor, env0: dict, chi_E: int, chi_I: int, n_sweeps: int,
-              h: np.ndarray, cutoff: float = 1e-12, adj_eps: float = 1e-12) -> torch.Tensor:
-    """A_cell: [Lx, Ly, p, D, D, D, D] float64 tensor (may require grad)."""
+              h: np.ndarray, cutoff: float = 1e-12, adj_eps: float = 1e-12, h_v=None) -> torch.Tensor:
+    """A_cell: [Lx, Ly, p, D, D, D, D] float64 tensor (may require grad);
+    h on horizontal bonds, h_v (default h) on vertical ones."""
     Lx, Ly = A_cell.shape[:2]
     A = {(x, y): A_cell[x, y] for x in range(Lx) for y in range(Ly)}
     env = {k: dict(v) for k, v in env0.items()}
     for _ in range(n_sweeps):
         env = sc.sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff, adj_eps)
-    e, _ = sc.energy(env, A, Lx, Ly, h)
+    e, _ = sc.energy(env, A, Lx, Ly, h, h_v)
     return e
 
 
 def energy_and_grad(A_np: np.ndarray, env0_np: dict, chi_E: int, chi_I: int, n_sweeps: int,
-                    h: np.ndarray, cutoff: float = 1e-12, adj_eps: float = 1e-12):
+                    h: np.ndarray, cutoff: float = 1e-12, adj_eps: float = 1e-12, h_v=None):
     A = torch.tensor(A_np, dtype=torch.float64, requires_grad=True)
     env0 = sc.env_from_numpy(env0_np)
-    e = energy_of(A, env0, chi_E, chi_I, n_sweeps, h, cutoff, adj_eps)
+    e = energy_of(A, env0, chi_E, chi_I, n_sweeps, h, cutoff, adj_eps, h_v)
     e.backward()
     return float(e), A.grad.detach().numpy().copy()
 

@@ -546,16 +546,23 @@ def bond_value(rho, h):
     return num / den
 
 
-def energy(env, A, Lx, Ly, h):
+def energy(env, A, Lx, Ly, h, h_v=None):
     """Energy per site: (1/(Lx Ly)) sum_{x,y} (e_h[x,y] + e_v[x,y]).
     Vertical bonds from rdm_vertical; horizontal bonds are vertical bonds of
-    the transposed frame.  Returns (e_site, {(x,y): (e_h, e_v)})."""
+    the transposed frame (so s1 is the left site of a horizontal bond and the
+    upper site of a vertical one).  h acts on the horizontal bonds and h_v
+    (default h) on the vertical ones: a lattice coarse-grained into the
+    square lattice, such as the honeycomb lattice with two sites per tensor
+    (p = 4, the benchmark model of the results section), couples different
+    sub-sites along the two directions.  Returns (e_site, {(x,y): (e_h, e_v)})."""
+    if h_v is None:
+        h_v = h
     bonds = {}
     et, At, lxt, lyt = frame_transpose(env, A, Lx, Ly)
     tot = 0.0
     for x in range(Lx):
         for y in range(Ly):
-            ev = bond_value(rdm_vertical(env, A, x, y, Lx, Ly), h)
+            ev = bond_value(rdm_vertical(env, A, x, y, Lx, Ly), h_v)
             eh = bond_value(rdm_vertical(et, At, y, x, lxt, lyt), h)
             bonds[(x, y)] = (eh, ev)
             tot = tot + eh + ev

@@ -22,7 +22,7 @@ INIT = {"identity": 0, "product": 1}
 
 EXPORTED = ("ctm_workspace_size", "ctm_init", "ctm_sweep", "ctm_projectors", "ctm_projectors_elems",
             "ctm_energy", "ctm_energy_grad", "ctm_env_elems", "ctm_env_export", "ctm_env_import",
-            "ctm_last_stats", "ctm_debug_gemm_work_bytes", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd", "ctm_debug_qr_work_bytes", "ctm_debug_qr",
+            "ctm_energy_hv", "ctm_energy_grad_hv", "ctm_last_stats", "ctm_debug_gemm_work_bytes", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd", "ctm_debug_qr_work_bytes", "ctm_debug_qr",
             "ctm_kernel_timing_enable", "ctm_kernel_timing", "ctm_destroy", "ctm_strerror")
 KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "gemm_bf16x3": 2, "jacobi_pair": 3,
                   "jacobi_rotate": 5, "gemm_bf16x6": 6}
@@ -61,6 +61,8 @@ def lib() -> ctypes.CDLL:
         "ctm_projectors_elems": (S, [cfgp]),
         "ctm_energy": (I, [P, P, ctypes.POINTER(D), P]),
         "ctm_energy_grad": (I, [P, P, I, I, ctypes.POINTER(D), P]),
+        "ctm_energy_hv": (I, [P, P, P, ctypes.POINTER(D), P]),
+        "ctm_energy_grad_hv": (I, [P, P, P, I, I, ctypes.POINTER(D), P]),
         "ctm_env_elems": (S, [cfgp]),
         "ctm_env_export": (I, [P, P]),
         "ctm_env_import": (I, [P, P]),
@@ -160,14 +162,18 @@ class SplitCTM:
             raise CtmError(st, "ctm_sweep")
         return st, n.value, d.value
 
-    def energy(self, h):
+    def energy(self, h, h_v=None):
+        """Energy per site; h on horizontal bonds, h_v (default h) on vertical ones."""
         hh = np.ascontiguousarray(h, dtype=np.float64)
+        hv = hh if h_v is None else np.ascontiguousarray(h_v, dtype=np.float64)
+        if hv.shape != hh.shape:
+            raise ValueError("h and h_v must have the same shape")
         e = ctypes.c_double(0.0)
         bonds = np.zeros((self.cfg.Lx, self.cfg.Ly, 2))
-        st = lib().ctm_energy(self.h, hh.ctypes.data_as(ctypes.c_void_p), ctypes.byref(e),
-                              bonds.ctypes.data_as(ctypes.c_void_p))
+        st = lib().ctm_energy_hv(self.h, hh.ctypes.data_as(ctypes.c_void_p), hv.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(e), bonds.ctypes.data_as(ctypes.c_void_p))
         if st != CTM_OK:
-            raise CtmError(st, "ctm_energy")
+            raise CtmError(st, "ctm_energy_hv")
         return e.value, bonds
 
     def projectors(self, direction, x, y):
@@ -188,15 +194,18 @@ class SplitCTM:
             off += k
         return res, te
 
-    def energy_grad(self, h, n_sweeps, ckpt_every=1):
+    def energy_grad(self, h, n_sweeps, ckpt_every=1, h_v=None):
         torch = self.torch
         hh = np.ascontiguousarray(h, dtype=np.float64)
+        hv = hh if h_v is None else np.ascontiguousarray(h_v, dtype=np.float64)
+        if hv.shape != hh.shape:
+            raise ValueError("h and h_v must have the same shape")
         e = ctypes.c_double(0.0)
         dA = torch.zeros_like(self.A)
-        st = lib().ctm_energy_grad(self.h, hh.ctypes.data_as(ctypes.c_void_p), n_sweeps, ckpt_every,
-                                   ctypes.byref(e), _ptr(dA))
+        st = lib().ctm_energy_grad_hv(self.h, hh.ctypes.data_as(ctypes.c_void_p), hv.ctypes.data_as(ctypes.c_void_p),
+                                      n_sweeps, ckpt_every, ctypes.byref(e), _ptr(dA))
         if st != CTM_OK:
-            raise CtmError(st, "ctm_energy_grad")
+            raise CtmError(st, "ctm_energy_grad_hv")
         return e.value, dA
 
     def env_export(self):

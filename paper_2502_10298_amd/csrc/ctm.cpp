@@ -49,7 +49,8 @@ struct ctm_ctx {
   Ten Aflat;               // contraction-dtype copy, same layout
   Ten cur_blk, start_blk;  // environments in the packed layout (contraction dtype)
   Ten spec_prev;           // FP64 corner spectra [Lx Ly 4][chiE]
-  Ten h64;                 // FP64 [p^2][p^2]
+  Ten h64;                 // FP64 [p^2][p^2], horizontal bonds
+  Ten h64v;                // FP64 [p^2][p^2], vertical bonds
   size_t transient_mark = 0;
   int host_flags[256];
   bool have_spec = false;
@@ -505,7 +506,7 @@ void energies(ctm_ctx& c, const Env& env, const Peps& A, std::vector<Ten>& eh, s
   eh.assign((size_t)c.Lx * c.Ly, Ten());
   ev.assign((size_t)c.Lx * c.Ly, Ten());
   for (int x = 0; x < c.Lx; ++x)
-    for (int y = 0; y < c.Ly; ++y) ev[(size_t)x * c.Ly + y] = E.bond_energy(vertical_rho(E, env, A, x, y), c.h64, c.p);
+    for (int y = 0; y < c.Ly; ++y) ev[(size_t)x * c.Ly + y] = E.bond_energy(vertical_rho(E, env, A, x, y), c.h64v, c.p);
   Env te;
   Peps ta;
   frame_transpose(E, env, A, te, ta);
@@ -599,6 +600,7 @@ void init_persistent(ctm_ctx* c, const double* A_dev, const double* bvec) {
   c->start_blk = E.alloc(E.cdt, {env_n});
   c->spec_prev = E.alloc(F64, {(long)c->Lx * c->Ly * 4 * c->chiE});
   c->h64 = E.alloc(F64, {(long)c->p * c->p * c->p * c->p});
+  c->h64v = E.alloc(F64, {(long)c->p * c->p * c->p * c->p});
   Ten part = E.alloc(F64, {(long)reduce_partials()});
   E.partial = part.f64();
   if (!E.dry && E.ok()) {
@@ -687,7 +689,8 @@ double corner_delta(ctm_ctx* c) {
 // ---------------------------------------------------------------------------
 // gradient: forward with checkpoints, then reverse move by move
 // ---------------------------------------------------------------------------
-ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, int n_sweeps, int ckpt, double* e_site, double* dA_dev) {
+ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_host, int n_sweeps, int ckpt,
+                            double* e_site, double* dA_dev) {
   Engine& E = c->E;
   if (n_sweeps < 0 || ckpt < 1) return CTM_EINVAL;
   const int nblk = (n_sweeps + ckpt - 1) / ckpt;
@@ -714,6 +717,7 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, int n_sweeps, int 
   E.zero(gA);
   if (!E.dry && E.ok()) {
     E.check(hipMemcpyAsync(c->h64.p, h_host, c->h64.bytes(), hipMemcpyHostToDevice, E.s));
+    E.check(hipMemcpyAsync(c->h64v.p, hv_host, c->h64v.bytes(), hipMemcpyHostToDevice, E.s));
     E.check(hipMemcpyAsync(ck[0].p, c->start_blk.p, c->start_blk.bytes(), hipMemcpyDeviceToDevice, E.s));
   }
   const Peps A = peps_view(*c, c->Aflat);
@@ -940,7 +944,7 @@ ctm_status ctm_workspace_size(const ctm_config* cfg, int with_grad, int n_sweeps
     left_column(*c, env, A, 0, &col, 0, -1);
     c->E.ar.release(mk);
   }
-  if (with_grad) energy_grad_impl(c, nullptr, n_sweeps, ckpt_every, nullptr, nullptr);
+  if (with_grad) energy_grad_impl(c, nullptr, nullptr, n_sweeps, ckpt_every, nullptr, nullptr);
   peak = std::max(peak, c->E.ar.peak);
   const int planning = c->E.status;
   delete c;
@@ -1013,10 +1017,15 @@ ctm_status ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, d
 }
 
 ctm_status ctm_energy(ctm_ctx* c, const double* h_host, double* e_site, double* e_bonds) {
-  if (!c || !h_host) return CTM_EINVAL;
+  return ctm_energy_hv(c, h_host, h_host, e_site, e_bonds);
+}
+
+ctm_status ctm_energy_hv(ctm_ctx* c, const double* h_host, const double* hv_host, double* e_site, double* e_bonds) {
+  if (!c || !h_host || !hv_host) return CTM_EINVAL;
   Engine& E = c->E;
   begin(c);
   if (E.ok()) E.check(hipMemcpyAsync(c->h64.p, h_host, c->h64.bytes(), hipMemcpyHostToDevice, E.s));
+  if (E.ok()) E.check(hipMemcpyAsync(c->h64v.p, hv_host, c->h64v.bytes(), hipMemcpyHostToDevice, E.s));
   const Peps A = peps_view(*c, c->Aflat);
   Env env = view_env(*c, c->cur_blk);
   std::vector<Ten> eh, ev;
@@ -1100,10 +1109,15 @@ ctm_status ctm_projectors(ctm_ctx* c, int direction, int x, int y, double* out_d
 
 ctm_status ctm_energy_grad(ctm_ctx* c, const double* h_host, int n_sweeps, int ckpt_every, double* e_site,
                            double* dA_dev) {
-  if (!c || !h_host || !dA_dev || n_sweeps < 0 || ckpt_every < 1) return CTM_EINVAL;
+  return ctm_energy_grad_hv(c, h_host, h_host, n_sweeps, ckpt_every, e_site, dA_dev);
+}
+
+ctm_status ctm_energy_grad_hv(ctm_ctx* c, const double* h_host, const double* hv_host, int n_sweeps, int ckpt_every,
+                              double* e_site, double* dA_dev) {
+  if (!c || !h_host || !hv_host || !dA_dev || n_sweeps < 0 || ckpt_every < 1) return CTM_EINVAL;
   begin(c);
   c->have_spec = false;
-  ctm_status st = energy_grad_impl(c, h_host, n_sweeps, ckpt_every, e_site, dA_dev);
+  ctm_status st = energy_grad_impl(c, h_host, hv_host, n_sweeps, ckpt_every, e_site, dA_dev);
   return finish(c, st);
 }
 

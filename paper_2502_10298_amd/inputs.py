@@ -137,6 +137,36 @@ def heisenberg_h_rotated() -> np.ndarray:
                             [-2, 0, 0, -1]], dtype=np.float64)
 
 
+def honeycomb_heisenberg_cg() -> tuple:
+    """Spin-1/2 Heisenberg model of the honeycomb lattice with two sites per
+    square-lattice tensor (p = 4, physical index 2 s_a + s_b), as bond
+    Hamiltonians (h_h, h_v) in the layout of heisenberg_h (rows (s1 s2) bra,
+    s1 = left / upper site).  Lattice: a(c)-b(c) inside a tensor,
+    b(c)-a(c + right) on horizontal bonds, a(c)-b(c + down) on vertical
+    bonds; every site then has three neighbours and the smallest loops are
+    hexagons.  The term inside a tensor is shared out as a quarter on each
+    of its four bonds, so the energy per site of the square lattice is the
+    energy per two honeycomb sites."""
+    sp = np.array([[0.0, 1.0], [0.0, 0.0]])   # S^+
+    sz = np.diag([0.5, -0.5])
+    i2 = np.eye(2)
+
+    def dot(x1, x2):
+        # S.S = S^z S^z + (S^+ S^- + S^- S^+) / 2 between the spin that x1
+        # places in the first 4-dimensional site and the one x2 places in the second
+        return np.kron(x1(sz), x2(sz)) + 0.5 * (np.kron(x1(sp), x2(sp.T)) + np.kron(x1(sp.T), x2(sp)))
+
+    on_a = lambda o: np.kron(o, i2)
+    on_b = lambda o: np.kron(i2, o)
+    # inside one tensor: S_a . S_b on the 4-dimensional site
+    h_in = np.kron(sz, sz) + 0.5 * (np.kron(sp, sp.T) + np.kron(sp.T, sp))
+    i4 = np.eye(4)
+    share = 0.25 * (np.kron(h_in, i4) + np.kron(i4, h_in))
+    h_h = dot(on_b, on_a) + share    # b(left) . a(right)
+    h_v = dot(on_a, on_b) + share    # a(upper) . b(lower)
+    return h_h, h_v
+
+
 def sz_sz() -> np.ndarray:
     """sigma^z (x) sigma^z, used for the Ising nearest-neighbour correlator."""
     return np.diag([1.0, -1.0, -1.0, 1.0])

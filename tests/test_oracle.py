@@ -231,6 +231,43 @@ def test_product_states_exact_energy(D):
     assert abs(float(e2) + 0.5) < 1e-12
 
 
+def test_honeycomb_coarse_grained_product_state_energy():
+    """Honeycomb Heisenberg model with two sites per tensor (p = 4; the bond
+    Hamiltonians differ between the horizontal and the vertical bonds and are
+    not symmetric under exchange of the two tensors).  For a product state of
+    real spinors every S_i.S_j is cos(theta_i - theta_j) / 4, so the energy of
+    every bond, and with it the orientation convention (s1 = left / upper
+    tensor), is fixed in closed form.  A 1 x 2 cell with four different spins."""
+    th = {("a", 0): 0.3, ("b", 0): 2.1, ("a", 1): -1.2, ("b", 1): 0.8}
+    spin = lambda t: np.array([np.cos(t / 2), np.sin(t / 2)])
+    A_np = np.zeros((1, 2, 4, 1, 1, 1, 1))
+    for y in range(2):
+        A_np[0, y, :, 0, 0, 0, 0] = np.kron(spin(th[("a", y)]), spin(th[("b", y)]))
+    A = sc.peps_from_numpy(A_np)
+    env = sc.init_identity(1, 2, 1)
+    env, _, _ = sc.run(env, A, 1, 2, 2, 2, 3)
+    h_h, h_v = inp.honeycomb_heisenberg_cg()
+    e, bonds = sc.energy(env, A, 1, 2, h_h, h_v)
+    dot = lambda u, v: np.cos(th[u] - th[v]) / 4
+    intra = [dot(("a", y), ("b", y)) for y in range(2)]
+    for y in range(2):
+        yr = (y + 1) % 2
+        # horizontal: b(left) . a(right) plus a quarter of each tensor's inner term
+        eh = dot(("b", y), ("a", yr)) + (intra[y] + intra[yr]) / 4
+        # vertical (one row, periodic): a(upper) . b(lower) of the same tensor
+        ev = dot(("a", y), ("b", y)) + intra[y] / 2
+        assert abs(float(bonds[(0, y)][0]) - eh) < 1e-12
+        assert abs(float(bonds[(0, y)][1]) - ev) < 1e-12
+    total = sum(intra) + sum(dot(("b", y), ("a", (y + 1) % 2)) for y in range(2)) + sum(intra)
+    assert abs(float(e) - total / 2) < 1e-12
+    # the same model with the two tensors swapped inside every bond gives other bond values
+    sw = lambda h: h.reshape(4, 4, 4, 4).transpose(1, 0, 3, 2).reshape(16, 16)
+    _, bonds_sw = sc.energy(env, A, 1, 2, sw(h_h), sw(h_v))
+    eh_sw = dot(("a", 0), ("b", 1)) + (intra[0] + intra[1]) / 4
+    assert abs(float(bonds_sw[(0, 0)][0]) - eh_sw) < 1e-12
+    assert abs(eh_sw - float(bonds[(0, 0)][0])) > 0.1
+
+
 @pytest.mark.parametrize("beta", [0.3, 0.6])
 def test_ising_free_energy_and_correlator(beta):
     """Square-root Boltzmann PEPS: <psi|psi> = Z_Ising, so the per-site log
