@@ -161,7 +161,7 @@ ctm_status ctm_debug_gemm(int prec, int transA, int transB, int M, int N, int K,
                           void* C, void* work, void* hip_stream);
 size_t ctm_debug_svd_work_bytes(int n, int batch);
 /* ctm_debug_qr: Householder QR of batch tall matrices X (m x k, k <= m <=
- * 4096) given transposed, Xt = X^T (k x m row-major, consecutive; overwritten
+ * 8192) given transposed, Xt = X^T (k x m row-major, consecutive; overwritten
  * by the reflectors and R).  R (k x k row-major, zero below the diagonal) and
  * Qt = Q^T (k x m) receive the thin factors (either may be NULL); work =
  * ctm_debug_qr_work_bytes bytes of device memory.  Synchronises the stream. */

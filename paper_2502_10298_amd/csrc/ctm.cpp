@@ -1189,7 +1189,7 @@ size_t ctm_debug_qr_work_bytes(int m, int k, int batch) {
 }
 
 ctm_status ctm_debug_qr(int m, int k, int batch, double* Xt, double* R, double* Qt, void* work, void* stream) {
-  if (m < k || k < 1 || batch < 1 || m > 4096 || !Xt || !work) return CTM_EINVAL;
+  if (m < k || k < 1 || batch < 1 || m > 8192 || !Xt || !work) return CTM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = qr_f64(s, m, k, batch, Xt, R, Qt, work);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -624,7 +624,7 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
     long r = 0;
     if (q.fX.p && q.fZ.p && q.rows) r = q.fZ.n() / ps[i].nb;
     else if (ps[i].na < ps[i].nb) r = ps[i].na;
-    if (r > 0 && r < ps[i].nb && ps[i].nb <= 4096 && lowrank_svd) r0[i] = r;
+    if (r > 0 && r < ps[i].nb && ps[i].nb <= 8192 && lowrank_svd) r0[i] = r;
   }
   // groups of equal (n_b, r0), in request order
   struct Group {

@@ -90,7 +90,7 @@ size_t svd_work_bytes(int n, int batch);
 size_t svd_precond_work_bytes(int n, int batch);
 hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, double* U, double* S, double* V,
                            void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out);
-// Householder QR of batch tall matrices X (m x k, m >= k, m <= 4096) given as
+// Householder QR of batch tall matrices X (m x k, m >= k, m <= 8192) given as
 // Xt = X^T (k x m row-major, overwritten).  R: k x k upper triangular
 // (row-major), Qt = Q^T (k x m); either may be null.
 size_t qr_work_bytes(int m, int k, int batch);

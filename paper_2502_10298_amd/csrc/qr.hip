@@ -470,7 +470,7 @@ static int w_slices(int nt, int len, int batch) {
 
 hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R, double* Qt, void* work) {
   if (m < k || k < 1 || batch < 1) return hipErrorInvalidValue;
-  if (m > 4096) return hipErrorInvalidValue;   // rows held in registers: at most 4 per thread
+  if (m > 8192) return hipErrorInvalidValue;   // rows held in registers: at most 8 per thread
   QrLayout L = qr_layout(m, k, batch);
   char* w = (char*)work;
   double* Vr = (double*)(w + L.offV);
@@ -483,7 +483,7 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
   hipError_t e = hipSuccess;
   // panels of 16 columns with 256 threads (up to 4 rows each) or 512 threads
   // (4 rows each, up to 2048 rows); beyond 2048 rows 1024 threads with 4
-  // columns; no panel crosses an outer block boundary
+  // columns (up to 8 rows each); no panel crosses an outer block boundary
   struct Panel {
     int p0, pw, nt_threads, rm;
   };
@@ -530,8 +530,12 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
       } else {
         if (P.rm <= 3)
           hipLaunchKernelGGL((qr_panel_kernel<1024, 3, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
-        else
+        else if (P.rm <= 4)
           hipLaunchKernelGGL((qr_panel_kernel<1024, 4, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
+        else if (P.rm <= 6)
+          hipLaunchKernelGGL((qr_panel_kernel<1024, 6, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
+        else
+          hipLaunchKernelGGL((qr_panel_kernel<1024, 8, 4>), g, dim3(1024), 0, s, Xt, Vr, T, tau, m, k, L.sX, L.sT, p0, pw);
       }
       e = hipGetLastError();
       const int nt = j1 - p0 - pw;   // rest of the outer block (rows of Xt)

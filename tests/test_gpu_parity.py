@@ -111,7 +111,8 @@ def test_jacobi_svd(n, batch):
 
 
 @pytest.mark.parametrize("m,k,batch", [(40, 17, 1), (300, 150, 3), (2048, 1024, 2), (3200, 160, 1), (64, 64, 2),
-                                       (200, 130, 2), (4096, 300, 1), (1024, 1024, 3), (2100, 200, 1)])
+                                       (200, 130, 2), (4096, 300, 1), (1024, 1024, 3), (2100, 200, 1),
+                                       (5440, 340, 1), (8192, 100, 2)])
 def test_householder_qr(m, k, batch):
     """X = Q R with Q orthonormal and R upper triangular, to working accuracy,
     on graded and rank-deficient inputs (panels of 16, 8 and 4 columns; outer
