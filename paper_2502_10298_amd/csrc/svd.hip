@@ -165,8 +165,10 @@ __device__ inline void jacobi_rot(double haa, double hcc, double hac, double thr
 // Gram: wave w takes entries [512 k + 64 w, +64) of the column length in
 // slice k (the same number of slices in every wave); the 64 x 32 block is
 // loaded in one go (the next slice's loads are issued before the current one
-// is multiplied), staged through LDS two 16-entry subs at a time into the
-// operand layout of v_mfma_f64_16x16x4 (A lane l holds A[l%16][l/16], B lane
+// is multiplied), staged through the wavefront's own LDS region (no
+// workgroup barrier, so the wavefronts drift apart and overlap their loads
+// and multiplies) two 16-entry subs at a time into the operand layout of
+// v_mfma_f64_16x16x4 (A lane l holds A[l%16][l/16], B lane
 // l holds B[l/16][l%16], D lane l register r holds D[4r + l/16][l%16]), and
 // accumulated per wave; the eight wave partials are summed in a fixed order.
 //
@@ -178,14 +180,26 @@ __device__ inline void jacobi_rot(double haa, double hcc, double hac, double thr
 static constexpr int JPT = 512;                 // threads of the pair kernel
 static constexpr int JSL = 64 * (JPT / 64);     // column-length entries per slice
 
+// Orders the LDS accesses of one wavefront around a point (its lanes exchange
+// data through the wavefront's own LDS region): a wavefront executes its LDS
+// instructions in order, so it suffices that the compiler neither moves
+// memory accesses across this point nor leaves the writes outstanding.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Raw loads of a wavefront's 64-entry slice of the pair's 32 columns
+// (entries past the end read the last one); they are zeroed when staged, so
+// that nothing waits for a prefetch before it is used.
 __device__ inline void gram_load(const double* Gp, const double* Gq, int m, int c0, int l, double (&v)[4][8]) {
 #pragma unroll
   for (int sub = 0; sub < 4; ++sub)
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int c = c0 + sub * 16 + (l & 15), cc = min(c, m - 1);
-      const double x = (i < 4) ? Gp[(long)(i * 4) * m + cc] : Gq[(long)((i - 4) * 4) * m + cc];
-      v[sub][i] = (c < m) ? x : 0.0;
+      const int cc = min(c0 + sub * 16 + (l & 15), m - 1);
+      v[sub][i] = (i < 4) ? Gp[(long)(i * 4) * m + cc] : Gq[(long)((i - 4) * 4) * m + cc];
     }
 }
 
@@ -222,8 +236,11 @@ __global__ __launch_bounds__(JPT) void jacobi_pair_kernel(const double* Gt_all, 
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) stg[(s2 * JP + i * 4 + (l >> 4)) * 17 + (l & 15)] = v[2 * half + s2][i];
-      __syncthreads();
+        for (int i = 0; i < 8; ++i) {
+          const bool in = k * JSL + wv * 64 + (2 * half + s2) * 16 + (l & 15) < m;
+          stg[(s2 * JP + i * 4 + (l >> 4)) * 17 + (l & 15)] = in ? v[2 * half + s2][i] : 0.0;
+        }
+      wave_lds_sync();   // the staging region is the wavefront's own
       if (half == 0 && k + 1 < nsl) gram_load(Gp, Gq, m, (k + 1) * JSL + wv * 64, l, vn);
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2) {
@@ -237,7 +254,7 @@ __global__ __launch_bounds__(JPT) void jacobi_pair_kernel(const double* Gt_all, 
           acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc11, 0, 0, 0);
         }
       }
-      __syncthreads();
+      wave_lds_sync();
     }
     if (k + 1 < nsl) {
 #pragma unroll
@@ -247,7 +264,9 @@ __global__ __launch_bounds__(JPT) void jacobi_pair_kernel(const double* Gt_all, 
     }
   }
   // wave partials of the tiles (0,0), (0,1), (1,1); the tile (1,0) is the
-  // transpose of (0,1) and is not formed
+  // transpose of (0,1) and is not formed.  They overwrite other wavefronts'
+  // staging regions: every wavefront must be done with its own first.
+  __syncthreads();
   double* wp = sm + wv * 768;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
