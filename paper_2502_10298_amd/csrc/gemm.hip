@@ -131,20 +131,35 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
     }
     __syncthreads();
   }
+  // f64 16x16x4: D[4 r + l / 16][l % 16]; f32 16x16x4: D[4 (l / 16) + r][l % 16].
+  // With beta != 0 all sixteen C entries of the thread are loaded (clamped
+  // addresses, no branches) before any is combined, so their latencies overlap.
+  T cold[2][2][4];
+  if (beta != T(0)) {
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = sizeof(T) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+          const int m = min(bm + wm * 32 + ti * 16 + row, M - 1), n = min(bn + wn * 32 + tj * 16 + (lane & 15), N - 1);
+          cold[ti][tj][r] = C[(long)m * ldc + n];
+        }
+  }
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // f64 16x16x4: D[4 r + l / 16][l % 16]; f32 16x16x4: D[4 (l / 16) + r][l % 16]
         const int row = sizeof(T) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
         int m = bm + wm * 32 + ti * 16 + row;
         int n = bn + wn * 32 + tj * 16 + (lane & 15);
         if (m < M && n < N) {
           T v = alpha * acc[ti][tj][r];
           long o = (long)m * ldc + n;
-          C[o] = (beta == T(0)) ? v : v + beta * C[o];
+          C[o] = (beta == T(0)) ? v : v + beta * cold[ti][tj][r];
         }
       }
 }
@@ -245,6 +260,19 @@ __global__ __launch_bounds__(256) void gemm_bf16s_kernel(int M, int N, int K, fl
       }
     __syncthreads();
   }
+  float cold[2][2][4];   // C entries loaded before any is combined (beta != 0)
+  if (beta != 0.f) {
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = min(bm + wm * 32 + ti * 16 + 4 * (lane >> 4) + r, M - 1);
+          const int n = min(bn + wn * 32 + tj * 16 + (lane & 15), N - 1);
+          cold[ti][tj][r] = C[(long)m * ldc + n];
+        }
+  }
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -256,7 +284,7 @@ __global__ __launch_bounds__(256) void gemm_bf16s_kernel(int M, int N, int K, fl
         if (m < M && n < N) {
           float v = alpha * acc[ti][tj][r];
           long o = (long)m * ldc + n;
-          C[o] = (beta == 0.f) ? v : v + beta * C[o];
+          C[o] = (beta == 0.f) ? v : v + beta * cold[ti][tj][r];
         }
       }
 }
@@ -544,7 +572,20 @@ __global__ __launch_bounds__(256) void gemm_bf16nt_kernel(int M, int N, int Kp, 
     buf ^= 1;
   }
 #pragma unroll
-  for (int ti = 0; ti < 4; ++ti)
+  for (int ti = 0; ti < 4; ++ti) {
+    // with beta != 0 the sixteen C entries of a row tile are loaded (clamped
+    // addresses) before any is combined, so their latencies overlap
+    float cold[4][4];
+    if (!P && beta != 0.f) {
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = min(bm + wm * 64 + ti * 16 + 4 * (lane >> 4) + r, M - 1);
+          const int n = min(bn + wn * 64 + tj * 16 + (lane & 15), N - 1);
+          cold[tj][r] = C[(long)m * ldc + n];
+        }
+    }
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
@@ -557,10 +598,11 @@ __global__ __launch_bounds__(256) void gemm_bf16nt_kernel(int M, int N, int Kp, 
           } else {
             const float v = alpha * acc[ti][tj][r];
             const long o = (long)m * ldc + n;
-            C[o] = (beta == 0.f) ? v : v + beta * C[o];
+            C[o] = (beta == 0.f) ? v : v + beta * cold[tj][r];
           }
         }
       }
+  }
 }
 
 struct Bf16BigPlan {

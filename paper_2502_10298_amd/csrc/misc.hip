@@ -282,10 +282,19 @@ template <typename T>
 __global__ void splitk_reduce_kernel(const T* P, int S, int M, int N, T alpha, T beta, T* C, long ldc) {
   const long mn = (long)M * N;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < mn; e += (long)gridDim.x * blockDim.x) {
-    T a = 0;
-    for (int k = 0; k < S; ++k) a += P[(long)k * mn + e];
     const long o = (e / N) * ldc + e % N;
-    C[o] = (beta == T(0)) ? alpha * a : alpha * a + beta * C[o];
+    const T c = (beta == T(0)) ? T(0) : C[o];
+    // slices added in order; eight loads in flight at a time
+    T a = 0;
+    for (int k0 = 0; k0 < S; k0 += 8) {
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = P[(long)min(k0 + q, S - 1) * mn + e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q < S) a += v[q];
+    }
+    C[o] = (beta == T(0)) ? alpha * a : alpha * a + beta * c;
   }
 }
 hipError_t splitk_reduce_f64(hipStream_t s, const double* P, int S, int M, int N, double alpha, double beta, double* C,
