@@ -187,10 +187,7 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
         if (q >= t) a += Ts[t][q] * d[q];
       Ts[t][j] = -tau * a;
     }
-    if (t == j) {
-      Ts[j][j] = tau;
-      tau_all[(long)b * k + c] = tau;
-    }
+    if (t == j) Ts[j][j] = tau;   // tau_all is written after the last column (no global store in the loop)
   };
   static_for(column, std::make_integer_sequence<int, PWT>{});
   __syncthreads();
@@ -210,6 +207,7 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
   for (int l = 0; l < w; ++l)
     for (int i = t; i < p0; i += NT) Vr[(long)(p0 + l) * m + i] = 0.0;
   for (int e = t; e < PW * PW; e += NT) Tp[e] = Ts[e / PW][e % PW];
+  if (t < w) tau_all[(long)b * k + p0 + t] = Ts[t][t];
 }
 
 // Partial products over chunks of the column length:
