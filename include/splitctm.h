@@ -152,7 +152,7 @@ ctm_status ctm_last_stats(ctm_ctx* ctx, double* gemm_flops, double* svd_sweeps);
  * for BF16X3 products of 2^31 multiply-adds or more with both output
  * dimensions >= 1024, on operands split once into k-contiguous bf16 planes
  * (128 x 128 tiles, K sliced when the tiles are few).
- * ctm_debug_svd: batch n x n FP64 matrices M (row-major, consecutive) ->
+ * ctm_debug_svd: batch n x n FP64 matrices M (n <= 4096, row-major, consecutive) ->
  * U S V^T, S descending; work = ctm_debug_svd_work_bytes bytes of device
  * memory; *sweeps in: sweep cap (<= 0: 60), out: sweeps run.  Both
  * synchronise the stream. */

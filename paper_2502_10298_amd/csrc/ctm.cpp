@@ -1198,7 +1198,7 @@ ctm_status ctm_debug_qr(int m, int k, int batch, double* Xt, double* R, double* 
 
 ctm_status ctm_debug_svd(int n, int batch, const double* M, double* U, double* S, double* V, void* work,
                          int* sweeps, void* stream) {
-  if (n < 1 || batch < 1 || batch > 256 || !M || !U || !S || !V || !work) return CTM_EINVAL;
+  if (n < 1 || n > 4096 || batch < 1 || batch > 256 || !M || !U || !S || !V || !work) return CTM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   int flags[256];
   const int max_sweeps = (sweeps && *sweeps > 0) ? *sweeps : 60;

@@ -570,6 +570,7 @@ __global__ void svd_scatter_kernel(const double* Gt_all, const double* Vt_all, c
 
 hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, double* S, double* V, void* work,
                    int max_sweeps, double tol, int* host_flags, int* sweeps_out, const double* V0) {
+  if (n < 1 || n > 4096) return hipErrorInvalidValue;   // the column ranks stage n norms in LDS
   if (!(tol > 0.0)) tol = 1.2e-16 * std::sqrt((double)n);   // ~ sqrt(m) eps: the rounding floor of a dot product
   SvdLayout L = layout(n, batch);
   char* w = (char*)work;
@@ -802,13 +803,12 @@ static PreLayout pre_layout(int n, int batch) {
 }
 
 size_t svd_precond_work_bytes(int n, int batch) {
-  return n <= 4096 ? pre_layout(n, batch).total : svd_work_bytes(n, batch);
+  return pre_layout(n, batch).total;
 }
 
 hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, double* U, double* S, double* V,
                            void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out) {
-  if (n > 4096)   // the QR holds the rows of a panel in registers
-    return svd_f64(s, n, batch, A, U, S, V, work, max_sweeps, tol, host_flags, sweeps_out, nullptr);
+  if (n < 1 || n > 4096) return hipErrorInvalidValue;   // the limit of svd_f64
   PreLayout L = pre_layout(n, batch);
   char* w = (char*)work;
   double* Xt = (double*)(w + L.offX);

@@ -47,3 +47,16 @@ def test_invalid_configs_rejected():
     for cfg in bad:
         with pytest.raises(b.CtmError):
             b.workspace_size(cfg)
+
+
+def test_debug_decompositions_reject_sizes_beyond_their_limits():
+    # the argument checks run before any device call, so the (never
+    # dereferenced) pointers may be dummies and no GPU is needed
+    import ctypes
+    L = b.lib()
+    d = ctypes.c_void_p(256)
+    sw = ctypes.c_int(0)
+    assert L.ctm_debug_svd(4097, 1, d, d, d, d, d, ctypes.byref(sw), None) == b.CTM_EINVAL
+    assert L.ctm_debug_svd(0, 1, d, d, d, d, d, ctypes.byref(sw), None) == b.CTM_EINVAL
+    assert L.ctm_debug_qr(8193, 16, 1, d, d, d, d, None) == b.CTM_EINVAL
+    assert L.ctm_debug_qr(16, 17, 1, d, d, d, d, None) == b.CTM_EINVAL   # k > m
