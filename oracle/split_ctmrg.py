@@ -31,6 +31,15 @@ Readings of the paper (it is silent or its figures are missing):
   * every new C / T is divided by its Frobenius norm;
   * one sweep = left, top, right, bottom move; convergence measure = largest
     2-norm change of the singular values of any corner.
+
+Alternative yellow / red projectors (App. B, Figs.
+alternativeConstructionYellowProjectors and
+alternativeConstructionRedProjectors; flag alt_yr): the yellow half networks
+are those of App. A, but the ket physical leg is cut together with the
+interlayer and D legs, so yellow truncates (chi_I, D, p) and M_yellow spans
+the remaining (D, chi_I) legs only.  The physical leg then rides on the
+intermediate T4^bra (and, mirrored, on T2^ket of the right environment) until
+the bra layer is absorbed, and red truncates (chi_I, D) only.
 """
 from __future__ import annotations
 
@@ -202,7 +211,7 @@ def _normalize(t):
     return t / torch.linalg.norm(t)
 
 
-def _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps):
+def _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps, alt_yr=False):
     """Green and yellow projectors of column y (left side, ket layer first) and
     the mirrored pair of the same column for its right side (bra layer first).
 
@@ -210,7 +219,8 @@ def _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps):
     Fig. constructionYellowProjectors.  Left side: green truncates (E, K) on
     the cut (x|x+1), yellow truncates (I, K) on the ket|bra cut of row x.
     Right side (the same half networks split the other way): green' truncates
-    (B, F), yellow' truncates (W, J)."""
+    (B, F), yellow' truncates (W, J).  With alt_yr (App. B) the physical leg
+    is cut with them: yellow truncates (I, K, P), yellow' (P, W, J)."""
     G, Y, Gr, Yr = {}, {}, {}, {}
     for x in range(Lx):
         xp = (x + 1) % Lx
@@ -220,16 +230,22 @@ def _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps):
         Gr[x] = projectors(gT.permute(2, 3, 0, 1), gB.permute(2, 3, 0, 1), 2, chi_E, cutoff, adj_eps)
         yT = rho_yellow_top(env[(x, y)], A[(x, y)])
         yB = rho_yellow_bottom(env[(x, y)], A[(x, y)])
-        Y[x] = projectors(yT, yB, 2, chi_I, cutoff, adj_eps)
-        Yr[x] = projectors(yT.permute(3, 4, 0, 1, 2), yB.permute(3, 4, 0, 1, 2), 2, chi_I,
-                           cutoff, adj_eps)
+        if alt_yr:
+            Y[x] = projectors(yT, yB, 3, chi_I, cutoff, adj_eps)
+            Yr[x] = projectors(yT.permute(2, 3, 4, 0, 1), yB.permute(2, 3, 4, 0, 1), 3, chi_I,
+                               cutoff, adj_eps)
+        else:
+            Y[x] = projectors(yT, yB, 2, chi_I, cutoff, adj_eps)
+            Yr[x] = projectors(yT.permute(3, 4, 0, 1, 2), yB.permute(3, 4, 0, 1, 2), 2, chi_I,
+                               cutoff, adj_eps)
     return G, Y, Gr, Yr
 
 
-def left_intermediate(env, A, Lx, y, G, Y):
+def left_intermediate(env, A, Lx, y, G, Y, alt_yr=False):
     """Ket half-step of column y: absorb the ket layer into the left
     environment and apply the first (green, yellow) projectors.
-    C1t[g,e], T4kt[g,S,Y,P] (P = open physical leg), T4bt[Y,w,g], C4t[g,q]."""
+    C1t[g,e], T4kt[g,S,Y,P] (P = open physical leg), T4bt[Y,w,g], C4t[g,q];
+    with alt_yr the open physical leg is on T4bt[Y,w,g,P] and T4kt is [g,S,Y]."""
     C1t, T4kt, T4bt, C4t = {}, {}, {}, {}
     for x in range(Lx):
         e, a = env[(x, y)], A[(x, y)]
@@ -237,17 +253,22 @@ def left_intermediate(env, A, Lx, y, G, Y):
         GT_dn, GB_dn = G[x][0], G[x][1]
         YT, YB = Y[x][0], Y[x][1]
         C1t[x] = ncon("ab,bce,acg->ge", e["C1"], e["T1k"], GT_up)
-        T4kt[x] = ncon("xya,PcykS,acg,xkY->gSYP", e["T4k"], a, GB_up, YT)
-        T4bt[x] = ncon("vwx,xkY,vkg->Ywg", e["T4b"], YB, GT_dn)
+        if alt_yr:
+            T4kt[x] = ncon("xya,PcykS,acg,xkPY->gSY", e["T4k"], a, GB_up, YT)
+            T4bt[x] = ncon("vwx,xkPY,vkg->YwgP", e["T4b"], YB, GT_dn)
+        else:
+            T4kt[x] = ncon("xya,PcykS,acg,xkY->gSYP", e["T4k"], a, GB_up, YT)
+            T4bt[x] = ncon("vwx,xkY,vkg->Ywg", e["T4b"], YB, GT_dn)
         C4t[x] = ncon("tv,qrt,vrg->gq", e["C4"], e["T3k"], GB_dn)
     return C1t, T4kt, T4bt, C4t
 
 
-def right_intermediate(env, A, Lx, y, Gr, Yr):
+def right_intermediate(env, A, Lx, y, Gr, Yr, alt_yr=False):
     """Bra half-step of the right environment of column y (mirror image of
     left_intermediate: the bra layer sits next to C2 and C3 on the top and
     bottom edges).  C2t[e,k] (left chi_I, down), T2kt[k,S,i] (up, ket.r, down),
-    T2bt[i,w,k,P] (up, bra.l, down, open physical leg), C3t[k,i] (up, left)."""
+    T2bt[i,w,k,P] (up, bra.l, down, open physical leg), C3t[k,i] (up, left);
+    with alt_yr the open physical leg is on T2kt[k,S,i,P] and T2bt is [i,w,k]."""
     C2t, T2kt, T2bt, C3t = {}, {}, {}, {}
     for x in range(Lx):
         e, a = env[(x, y)], A[(x, y)]
@@ -255,23 +276,29 @@ def right_intermediate(env, A, Lx, y, Gr, Yr):
         GT_dn, GB_dn = Gr[x][0], Gr[x][1]
         YT, YB = Yr[x][0], Yr[x][1]
         C2t[x] = ncon("gF,eBg,BFk->ek", e["C2"], e["T1b"], GT_up)
-        T2kt[x] = ncon("FSJ,WFk,WJi->kSi", e["T2k"], GB_up, YT)
-        T2bt[x] = ncon("JkF,PWwBk,WJi,BFg->iwgP", e["T2b"], a, YB, GT_dn)
+        if alt_yr:
+            T2kt[x] = ncon("FSJ,WFk,PWJi->kSiP", e["T2k"], GB_up, YT)
+            T2bt[x] = ncon("JkF,PWwBk,PWJi,BFg->iwg", e["T2b"], a, YB, GT_dn)
+        else:
+            T2kt[x] = ncon("FSJ,WFk,WJi->kSi", e["T2k"], GB_up, YT)
+            T2bt[x] = ncon("JkF,PWwBk,WJi,BFg->iwgP", e["T2b"], a, YB, GT_dn)
         C3t[x] = ncon("Fq,qBi,BFk->ki", e["C3"], e["T3b"], GB_dn)
     return C2t, T2kt, T2bt, C3t
 
 
-def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12):
+def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, alt_yr=False):
     """Steps 1-3 of the left move of column y: green / yellow projectors,
     intermediate environments, teal / red projectors.  Returns
     (G, Y, TH, R, left intermediate env); G[x], TH[x] belong to the cut
-    (x|x+1), Y[x], R[x] to row x; each is (P_T, P_B, S, k)."""
+    (x|x+1), Y[x], R[x] to row x; each is (P_T, P_B, S, k).  With alt_yr
+    the teal networks carry the physical legs on the other intermediate
+    tensors, and red truncates (Y, W) of the networks below."""
     yn = (y + 1) % Ly
-    G, Y, Gr, Yr = _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps)
+    G, Y, Gr, Yr = _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps, alt_yr)
     if yn != y:
-        Gr, Yr = _first_projectors(env, A, Lx, yn, chi_E, chi_I, cutoff, adj_eps)[2:]
-    C1t, T4kt, T4bt, C4t = left_intermediate(env, A, Lx, y, G, Y)
-    C2t, T2kt, T2bt, C3t = right_intermediate(env, A, Lx, yn, Gr, Yr)
+        Gr, Yr = _first_projectors(env, A, Lx, yn, chi_E, chi_I, cutoff, adj_eps, alt_yr)[2:]
+    C1t, T4kt, T4bt, C4t = left_intermediate(env, A, Lx, y, G, Y, alt_yr)
+    C2t, T2kt, T2bt, C3t = right_intermediate(env, A, Lx, yn, Gr, Yr, alt_yr)
     TH, R = {}, {}
     for x in range(Lx):
         xp = (x + 1) % Lx
@@ -279,31 +306,47 @@ def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-
         n, np_ = env[(x, yn)], env[(xp, yn)]       # middle: ket part of column y+1
         b, bp = A[(x, y)], A[(xp, y)]
         k, kp = A[(x, yn)], A[(xp, yn)]
-        rT = ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
-                  C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
-                  T2kt[x], T2bt[x])
-        rB = ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
-                  T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
-                  T2kt[xp], T2bt[xp])
+        if alt_yr:
+            rT = ncon("ae,efh,hci,ij,aSY,YwGP,PfwBk,QcSKr,jrZQ,ZkF->GBKF",
+                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
+                      T2kt[x], T2bt[x])
+            rB = ncon("GSY,YwvP,vq,hoq,iXh,ni,PBwok,QKSXr,FrZQ,Zkn->GBKF",
+                      T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
+                      T2kt[xp], T2bt[xp])
+            sT = ncon("ae,eWh,hci,ij,aSY,QcSKr,jrJQ->YWKJ",
+                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
+            sB = ncon("YwvP,vq,hoq,iKh,ni,PWwok,Jkn->YWKJ",
+                      T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
+            n_red = 2
+        else:
+            rT = ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
+                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
+                      T2kt[x], T2bt[x])
+            rB = ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
+                      T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
+                      T2kt[xp], T2bt[xp])
+            sT = ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
+                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
+            sB = ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
+                      T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
+            n_red = 3
         TH[x] = projectors(rT, rB, 2, chi_E, cutoff, adj_eps)
-        sT = ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
-                  C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
-        sB = ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
-                  T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
-        R[x] = projectors(sT, sB, 3, chi_I, cutoff, adj_eps)
+        R[x] = projectors(sT, sB, n_red, chi_I, cutoff, adj_eps)
     return G, Y, TH, R, (C1t, T4kt, T4bt, C4t)
 
 
 def left_move(env: Dict, A: Dict, Lx: int, Ly: int, chi_E: int, chi_I: int,
-              cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None):
+              cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None,
+              alt_yr: bool = False):
     """Absorb every column of the cell into the left environment, in place,
     one column after the other (left_move_column)."""
     for y in range(Ly):
-        left_move_column(env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps, info)
+        left_move_column(env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps, info, alt_yr)
 
 
 def left_move_column(env: Dict, A: Dict, Lx: int, Ly: int, y: int, chi_E: int, chi_I: int,
-                     cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None):
+                     cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None,
+                     alt_yr: bool = False):
     """Absorb column y into the left environment of column y+1, in place.
 
     Every row x:
@@ -316,20 +359,28 @@ def left_move_column(env: Dict, A: Dict, Lx: int, Ly: int, y: int, chi_E: int, c
             [left env after ket step][bra of column y][ket of column y+1][right env after bra step]
          (App. A: these half networks contain the first projectors; the b
          legs are (D, chi_E) for teal and (D, p, chi_I) for red);
-      4. bra half-step: new C1, T4k, T4b, C4 of site [x, y+1], normalised."""
+      4. bra half-step: new C1, T4k, T4b, C4 of site [x, y+1], normalised.
+    alt_yr: the alternative yellow / red projectors of App. B (module
+    docstring)."""
     yn = (y + 1) % Ly
     G, Y, TH, R, (C1t, T4kt, T4bt, C4t) = column_projectors(
-        env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps)
+        env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps, alt_yr)
     new = {}
     for x in range(Lx):
         e, a = env[(x, y)], A[(x, y)]
         ThT_up, ThB_up = TH[(x - 1) % Lx][0], TH[(x - 1) % Lx][1]
         ThT_dn, ThB_dn = TH[x][0], TH[x][1]
         RT, RB = R[x][0], R[x][1]
+        if alt_yr:
+            T4k = ncon("gSY,gWU,YWD->DSU", T4kt[x], ThB_up, RT)
+            T4b = ncon("YwgP,PWwBs,YWU,gBD->DsU", T4bt[x], a, RB, ThT_dn)
+        else:
+            T4k = ncon("gSYP,gWU,YPWD->DSU", T4kt[x], ThB_up, RT)
+            T4b = ncon("Ywg,PWwBs,YPWU,gBD->DsU", T4bt[x], a, RB, ThT_dn)
         new[x] = dict(
             C1=_normalize(ncon("ge,efR,gfD->DR", C1t[x], e["T1b"], ThT_up)),
-            T4k=_normalize(ncon("gSYP,gWU,YPWD->DSU", T4kt[x], ThB_up, RT)),
-            T4b=_normalize(ncon("Ywg,PWwBs,YPWU,gBD->DsU", T4bt[x], a, RB, ThT_dn)),
+            T4k=_normalize(T4k),
+            T4b=_normalize(T4b),
             C4=_normalize(ncon("gq,Roq,goU->RU", C4t[x], e["T3b"], ThB_dn)),
         )
     if info is not None:
@@ -411,9 +462,10 @@ def from_frame(direction: str, env, A, Lx, Ly):
     raise ValueError(direction)
 
 
-def move(direction: str, env, A, Lx, Ly, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, info=None):
+def move(direction: str, env, A, Lx, Ly, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, info=None,
+         alt_yr=False):
     e2, a2, lx, ly = to_frame(direction, env, A, Lx, Ly)
-    left_move(e2, a2, lx, ly, chi_E, chi_I, cutoff, adj_eps, info)
+    left_move(e2, a2, lx, ly, chi_E, chi_I, cutoff, adj_eps, info, alt_yr)
     e3, _, _, _ = from_frame(direction, e2, a2, lx, ly)
     return e3
 
@@ -444,21 +496,21 @@ def spectra_delta(s_old, s_new) -> float:
     return d
 
 
-def sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, info=None):
+def sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, info=None, alt_yr=False):
     """One directional split-CTMRG step: left, top, right and bottom moves."""
     for direction in ("left", "top", "right", "bottom"):
-        env = move(direction, env, A, Lx, Ly, chi_E, chi_I, cutoff, adj_eps, info)
+        env = move(direction, env, A, Lx, Ly, chi_E, chi_I, cutoff, adj_eps, info, alt_yr)
     return env
 
 
-def run(env, A, Lx, Ly, chi_E, chi_I, max_sweeps, tol=0.0, cutoff=1e-12):
+def run(env, A, Lx, Ly, chi_E, chi_I, max_sweeps, tol=0.0, cutoff=1e-12, alt_yr=False):
     """Iterate sweeps until the corner spectra change by less than tol.
     Returns (env, sweeps_done, delta)."""
     s_old = corner_spectra(env)
     delta = math.inf
     done = 0
     for _ in range(max_sweeps):
-        env = sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff)
+        env = sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff, alt_yr=alt_yr)
         done += 1
         s_new = corner_spectra(env)
         delta = spectra_delta(s_old, s_new)

@@ -169,6 +169,37 @@ def test_half_steps_exact_without_truncation():
     assert abs(float(n2 - n0)) < 1e-8 * abs(float(n0))
 
 
+def test_alternative_half_steps_exact_without_truncation():
+    """App. B construction: yellow truncates (I, K, P) and yellow' (P, W, J);
+    the physical leg then sits on T4bt (left) and on T2kt (right).  Without
+    truncation the intermediate environments still close the 2-row patch
+    exactly, and the first projectors keep rank D chi (the (W, J) and (I, K)
+    dimensions that M_yellow spans)."""
+    D, chi = 2, 2
+    A = sc.peps_from_numpy(inp.peps_gaussian(21, 1, 1, 2, D))
+    env = sc.env_from_numpy(inp.random_env(22, 1, 1, D, chi, chi))
+    a, e = A[(0, 0)], env[(0, 0)]
+    big = 64
+    G, Y, Gr, Yr = sc._first_projectors(env, A, 1, 0, big, big, 1e-14, 1e-12, alt_yr=True)
+    assert Y[0][0].shape == (chi, D, 2, chi * D) and Yr[0][0].shape == (2, D, chi, chi * D)
+    n0 = sc.ncon("EKBF,EKBF->", sc.rho_green_top(e, a), sc.rho_green_bottom(e, a))
+    C1t, T4kt, T4bt, C4t = sc.left_intermediate(env, A, 1, 0, G, Y, alt_yr=True)
+    assert T4kt[0].dim() == 3 and T4bt[0].dim() == 4
+    top = sc.ncon("ae,efg,gh,hij,aiY,YwGz,zfwBk,jkF->GBF",
+                  C1t[0], e["T1b"], e["C2"], e["T2k"], T4kt[0], T4bt[0], a, e["T2b"])
+    bot = sc.ncon("GiY,Ywvz,vq,noq,mn,jkm,Fij,zBwok->GBF",
+                  T4kt[0], T4bt[0], C4t[0], e["T3b"], e["C3"], e["T2b"], e["T2k"], a)
+    n1 = sc.ncon("GBF,GBF->", top, bot)
+    assert abs(float(n1 - n0)) < 1e-8 * abs(float(n0))
+    C2t, T2kt, T2bt, C3t = sc.right_intermediate(env, A, 1, 0, Gr, Yr, alt_yr=True)
+    top = sc.ncon("ab,bce,eh,xya,Ewx,zcyKi,hiZz,ZwF->EKF",
+                  e["C1"], e["T1k"], C2t[0], e["T4k"], e["T4b"], a, T2kt[0], T2bt[0])
+    bot = sc.ncon("xyE,vwx,tv,qrt,nq,FiZQ,Zwn,QKyri->EKF",
+                  e["T4k"], e["T4b"], e["C4"], e["T3k"], C3t[0], T2kt[0], T2bt[0], a)
+    n2 = sc.ncon("EKF,EKF->", top, bot)
+    assert abs(float(n2 - n0)) < 1e-8 * abs(float(n0))
+
+
 # ---------------------------------------------------------------------------
 # lattice-symmetry frames
 # ---------------------------------------------------------------------------
@@ -218,13 +249,15 @@ def test_direction_maps_on_c4v_symmetric_state():
 # ---------------------------------------------------------------------------
 # whole CTMRG: closed forms
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("alt_yr", [False, True])
 @pytest.mark.parametrize("D", [1, 2])
-def test_product_states_exact_energy(D):
+def test_product_states_exact_energy(D, alt_yr):
     """Rank-1 virtual structure: the state is a product of identical real
-    spinors; each bond gives +1/4 for S.S and -1/4 in the rotated frame."""
+    spinors; each bond gives +1/4 for S.S and -1/4 in the rotated frame
+    (with either yellow / red construction)."""
     A = sc.peps_from_numpy(inp.peps_product(3 + D, 2, D))
     env = sc.init_identity(1, 1, D)
-    env, _, _ = sc.run(env, A, 1, 1, 6, 6, 4)
+    env, _, _ = sc.run(env, A, 1, 1, 6, 6, 4, alt_yr=alt_yr)
     e, _ = sc.energy(env, A, 1, 1, inp.heisenberg_h())
     e2, _ = sc.energy(env, A, 1, 1, inp.heisenberg_h_rotated())
     assert abs(float(e) - 0.5) < 1e-12
@@ -268,13 +301,13 @@ def test_honeycomb_coarse_grained_product_state_energy():
     assert abs(eh_sw - float(bonds[(0, 0)][0])) > 0.1
 
 
-@pytest.mark.parametrize("beta", [0.3, 0.6])
-def test_ising_free_energy_and_correlator(beta):
+@pytest.mark.parametrize("beta,alt_yr", [(0.3, False), (0.6, False), (0.3, True)])
+def test_ising_free_energy_and_correlator(beta, alt_yr):
     """Square-root Boltzmann PEPS: <psi|psi> = Z_Ising, so the per-site log
     partition function and the nearest-neighbour correlator are Onsager's."""
     A = sc.peps_from_numpy(inp.peps_ising(beta))
     env = sc.init_identity(1, 1, 2)
-    env, _, _ = sc.run(env, A, 1, 1, 16, 16, 60)
+    env, _, _ = sc.run(env, A, 1, 1, 16, 16, 60, alt_yr=alt_yr)
     lk = float(sc.log_kappa(env[(0, 0)], A[(0, 0)]))
     _, b = sc.energy(env, A, 1, 1, inp.sz_sz())
     eh, ev = (float(t) for t in b[(0, 0)])
@@ -346,6 +379,27 @@ def test_split_converges_to_conventional_as_chi_grows():
     assert diffs[2] < 1e-7
 
 
+@pytest.mark.slow
+def test_alternative_yellow_red_converges_to_conventional_as_chi_grows():
+    """App. B: with the physical leg cut by the yellow projectors (which then
+    compress (chi_I, D, p) through the (D, chi_I) legs of M_yellow) the split
+    CTMRG still reaches the conventional fixed point as chi = chi_E = chi_I
+    grows; a wrong leg in any of its networks breaks this."""
+    A_np = inp.peps_gaussian(7, 1, 1, 2, 2)
+    h = inp.heisenberg_h_rotated()
+    env_c, Ad = cc.run(A_np, 16, 40)
+    e_ref = cc.energy(env_c, Ad, 1, 1, h)
+    A = sc.peps_from_numpy(A_np)
+    diffs = []
+    for chi in (4, 8, 16):
+        env = sc.init_identity(1, 1, 2)
+        env, _, _ = sc.run(env, A, 1, 1, chi, chi, 40, alt_yr=True)
+        es, _ = sc.energy(env, A, 1, 1, h)
+        diffs.append(abs(float(es) - e_ref) / abs(e_ref))
+    assert diffs[0] > diffs[1] > diffs[2]
+    assert diffs[2] < 1e-7
+
+
 def test_translation_invariant_2x2_cell_equals_1x1():
     """A 2x2 cell filled with one tensor is the 1x1 problem: the unit-cell
     bookkeeping (columns in sequence, per-site environments) must reach the
@@ -387,6 +441,23 @@ def test_gradient_matches_finite_differences_and_scale_invariance():
         dirs.append(d.reshape(A.shape))
     for d in dirs:
         fd = og.central_difference4(A, env0, chi, chi, ns, h, d, step=1e-5)
+        an = float((g * d).sum())
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3 * np.linalg.norm(g)), (fd, an)
+
+
+def test_alternative_construction_gradient_matches_finite_differences():
+    """Reverse mode through the App. B construction (two sweeps from the
+    fixed random start of the test above) against a fourth-order central
+    difference."""
+    A = inp.peps_gaussian(11, 1, 1, 2, 2)
+    chi, ns = 4, 2
+    env0 = inp.random_env(5, 1, 1, 2, chi, chi)
+    h = inp.heisenberg_h_rotated()
+    e, g = og.energy_and_grad(A, env0, chi, chi, ns, h, alt_yr=True)
+    assert abs(float((A * g).sum())) < 1e-10 * np.linalg.norm(A) * np.linalg.norm(g)
+    rng = np.random.default_rng(1)
+    for d in [rng.standard_normal(A.shape) for _ in range(2)]:
+        fd = og.central_difference4(A, env0, chi, chi, ns, h, d, step=1e-5, alt_yr=True)
         an = float((g * d).sum())
         assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3 * np.linalg.norm(g)), (fd, an)
 
