@@ -70,6 +70,16 @@ typedef enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16X3 = 2, CTM_BF16X6 = 3 } ctm_
  * passed in with ctm_env_import. */
 typedef enum { CTM_INIT_IDENTITY = 0, CTM_INIT_PRODUCT = 1 } ctm_init_mode;
 
+/* Yellow / red projector construction.  APP_A: the networks of App. A
+ * (Figs. constructionYellowProjectors, constructionRedProjectors): yellow
+ * truncates (chi_I, D), red truncates (chi_I, p, D).  ALT_YR: the alternative
+ * of App. B (Figs. alternativeConstructionYellowProjectors,
+ * alternativeConstructionRedProjectors): the same yellow networks, but the
+ * physical leg is cut together with (chi_I, D), so M_yellow spans only the
+ * (D, chi_I) legs, and red truncates (chi_I, D); no SVD then carries the p
+ * factor. */
+typedef enum { CTM_PROJ_APP_A = 0, CTM_PROJ_ALT_YR = 1 } ctm_projector_variant;
+
 typedef struct {
   int Lx, Ly;                  /* unit cell: rows, columns */
   int p, D;                    /* physical and bulk bond dimension */
@@ -78,6 +88,7 @@ typedef struct {
   double svd_rel_cutoff;       /* drop singular values below cutoff * s_1 (<= 0: 1e-12) */
   double svd_adj_eps;          /* Lorentzian broadening of the SVD adjoint (<= 0: 1e-12) */
   ctm_init_mode init;
+  ctm_projector_variant projector_variant;
 } ctm_config;
 
 typedef struct ctm_ctx ctm_ctx;
@@ -102,7 +113,8 @@ ctm_status ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done,
  * site [x][y] (in that move's frame), from the current environment, which is
  * not modified.  out_dev (FP64, device) receives, in order, green P_T, P_B
  * [chi_E][D][chi_E], teal P_T, P_B [chi_E][D][chi_E], yellow P_T, P_B
- * [chi_I][D][chi_I] and red P_T, P_B [chi_I][p][D][chi_I]; columns beyond the
+ * [chi_I][D][chi_I] and red P_T, P_B [chi_I][p][D][chi_I] (ALT_YR: yellow
+ * [chi_I][D][p][chi_I], red [chi_I][D][chi_I]); columns beyond the
  * kept rank are zero.  trunc_err_host[4] = discarded weight sum_{k>=kept}
  * s_k^2 / sum s_k^2 of green, teal, yellow, red. */
 ctm_status ctm_projectors(ctm_ctx* ctx, int direction, int x, int y, double* out_dev, double* trunc_err_host);

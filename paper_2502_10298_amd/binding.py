@@ -37,7 +37,8 @@ class CtmError(RuntimeError):
 class ctm_config(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("p", ctypes.c_int), ("D", ctypes.c_int),
                 ("chi_E", ctypes.c_int), ("chi_I", ctypes.c_int), ("contract_prec", ctypes.c_int),
-                ("svd_rel_cutoff", ctypes.c_double), ("svd_adj_eps", ctypes.c_double), ("init", ctypes.c_int)]
+                ("svd_rel_cutoff", ctypes.c_double), ("svd_adj_eps", ctypes.c_double), ("init", ctypes.c_int),
+                ("projector_variant", ctypes.c_int)]
 
 
 _lib = None
@@ -90,8 +91,10 @@ def strerror(status: int) -> str:
     return lib().ctm_strerror(status).decode()
 
 
-def make_config(Lx, Ly, p, D, chi_E, chi_I, prec="fp64", init="identity", cutoff=1e-12, adj_eps=1e-12):
-    return ctm_config(Lx, Ly, p, D, chi_E, chi_I, PREC[prec], cutoff, adj_eps, INIT[init])
+def make_config(Lx, Ly, p, D, chi_E, chi_I, prec="fp64", init="identity", cutoff=1e-12, adj_eps=1e-12,
+                alt_yr=False):
+    """alt_yr: the alternative yellow / red projectors of App. B."""
+    return ctm_config(Lx, Ly, p, D, chi_E, chi_I, PREC[prec], cutoff, adj_eps, INIT[init], 1 if alt_yr else 0)
 
 
 def workspace_size(cfg: ctm_config, with_grad=False, n_sweeps=0, ckpt_every=1) -> int:
@@ -114,18 +117,19 @@ def _ptr(t):
 class SplitCTM:
     """One split-CTMRG context on the current HIP device.
 
-    A: torch FP64 tensor [Lx, Ly, p, D, D, D, D] on the GPU (copied at init)."""
+    A: torch FP64 tensor [Lx, Ly, p, D, D, D, D] on the GPU (copied at init).
+    alt_yr: the alternative yellow / red projectors of App. B."""
 
     def __init__(self, A, chi_E, chi_I=None, prec="fp64", init="identity", boundary=None,
                  with_grad=False, n_sweeps=0, ckpt_every=1, cutoff=1e-12, adj_eps=1e-12,
-                 workspace_bytes=None, stream=None):
+                 workspace_bytes=None, stream=None, alt_yr=False):
         import torch
         self.torch = torch
         if A.dtype != torch.float64 or not A.is_cuda or A.dim() != 7:
             raise ValueError("A must be a CUDA float64 tensor [Lx, Ly, p, D, D, D, D]")
         Lx, Ly, p, D = A.shape[:4]
         self.cfg = make_config(Lx, Ly, p, D, chi_E, chi_I if chi_I is not None else chi_E, prec, init,
-                               cutoff, adj_eps)
+                               cutoff, adj_eps, alt_yr)
         need = workspace_size(self.cfg, with_grad, n_sweeps, ckpt_every)
         self.ws_bytes = int(workspace_bytes) if workspace_bytes is not None else need
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=A.device)
@@ -185,7 +189,10 @@ class SplitCTM:
         if st != CTM_OK:
             raise CtmError(st, "ctm_projectors")
         c = self.cfg
-        shapes = [(c.chi_E, c.D, c.chi_E)] * 4 + [(c.chi_I, c.D, c.chi_I)] * 2 + [(c.chi_I, c.p, c.D, c.chi_I)] * 2
+        if c.projector_variant == 1:   # App. B: the physical leg is cut by yellow
+            shapes = [(c.chi_E, c.D, c.chi_E)] * 4 + [(c.chi_I, c.D, c.p, c.chi_I)] * 2 + [(c.chi_I, c.D, c.chi_I)] * 2
+        else:
+            shapes = [(c.chi_E, c.D, c.chi_E)] * 4 + [(c.chi_I, c.D, c.chi_I)] * 2 + [(c.chi_I, c.p, c.D, c.chi_I)] * 2
         names = ["green_T", "green_B", "teal_T", "teal_B", "yellow_T", "yellow_B", "red_T", "red_B"]
         res, off = {}, 0
         for nm, sh in zip(names, shapes):

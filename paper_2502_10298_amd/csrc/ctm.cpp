@@ -344,6 +344,11 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
   const int Lx = env.Lx, Ly = env.Ly, ce = c.chiE, ci = c.chiI;
   const int yn = (y + 1) % Ly;
   const bool spectra = col != nullptr;
+  // App. B alternative: yellow (yellow') also cuts the ket (bra) physical
+  // leg, which then rides on T4bt (T2kt) until the other layer is absorbed,
+  // and red truncates (chi_I, D) only
+  const bool alt = c.cfg.projector_variant == CTM_PROJ_ALT_YR;
+  const int ny = alt ? 3 : 2;
   std::vector<Ten> gT(Lx), gB(Lx), yT(Lx), yB(Lx), gT2, gB2, yT2, yB2;
   for (int x = 0; x < Lx; ++x) {
     gT[x] = rho_green_top(E, env.at(x, y), A.at(x, y));
@@ -379,8 +384,8 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
       const int xp = (x + 1) % Lx;
       rq.push_back({gT[x], gB[xp], 2, true, ce, spectra ? &sG[x] : nullptr});
       rq.push_back({gT2[x], gB2[xp], 2, false, ce, nullptr});
-      rq.push_back({yT[x], yB[x], 2, true, ci, spectra ? &sY[x] : nullptr});
-      rq.push_back({yT2[x], yB2[x], 2, false, ci, nullptr});
+      rq.push_back({yT[x], yB[x], ny, true, ci, spectra ? &sY[x] : nullptr});
+      rq.push_back({yT2[x], yB2[x], ny, false, ci, nullptr});
     }
     auto out = E.projectors_batch(rq);
     for (int x = 0; x < Lx; ++x) {
@@ -397,8 +402,13 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
     const Ten& a = A.at(x, y);
     const int xu = (x - 1 + Lx) % Lx;
     C1t[x] = E.ncon("ab,bce,acg->ge", {e.t[C1], e.t[T1k], G[xu][0]});
-    T4kt[x] = E.ncon("xya,PcykS,acg,xkY->gSYP", {e.t[T4k], a, G[xu][1], Y[x][0]});
-    T4bt[x] = E.ncon("vwx,xkY,vkg->Ywg", {e.t[T4b], Y[x][1], G[x][0]});
+    if (alt) {
+      T4kt[x] = E.ncon("xya,PcykS,acg,xkPY->gSY", {e.t[T4k], a, G[xu][1], Y[x][0]});
+      T4bt[x] = E.ncon("vwx,xkPY,vkg->YwgP", {e.t[T4b], Y[x][1], G[x][0]});
+    } else {
+      T4kt[x] = E.ncon("xya,PcykS,acg,xkY->gSYP", {e.t[T4k], a, G[xu][1], Y[x][0]});
+      T4bt[x] = E.ncon("vwx,xkY,vkg->Ywg", {e.t[T4b], Y[x][1], G[x][0]});
+    }
     C4t[x] = E.ncon("tv,qrt,vrg->gq", {e.t[C4], e.t[T3k], G[x][1]});
   }
   // bra half-step of the right environment of column y+1 (mirror image)
@@ -408,8 +418,13 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
     const Ten& a = A.at(x, yn);
     const int xu = (x - 1 + Lx) % Lx;
     C2t[x] = E.ncon("gF,eBg,BFk->ek", {e.t[C2], e.t[T1b], Gr[xu][0]});
-    T2kt[x] = E.ncon("FSJ,WFk,WJi->kSi", {e.t[T2k], Gr[xu][1], Yr[x][0]});
-    T2bt[x] = E.ncon("JkF,PWwBk,WJi,BFg->iwgP", {e.t[T2b], a, Yr[x][1], Gr[x][0]});
+    if (alt) {
+      T2kt[x] = E.ncon("FSJ,WFk,PWJi->kSiP", {e.t[T2k], Gr[xu][1], Yr[x][0]});
+      T2bt[x] = E.ncon("JkF,PWwBk,PWJi,BFg->iwg", {e.t[T2b], a, Yr[x][1], Gr[x][0]});
+    } else {
+      T2kt[x] = E.ncon("FSJ,WFk,WJi->kSi", {e.t[T2k], Gr[xu][1], Yr[x][0]});
+      T2bt[x] = E.ncon("JkF,PWwBk,WJi,BFg->iwgP", {e.t[T2b], a, Yr[x][1], Gr[x][0]});
+    }
     C3t[x] = E.ncon("Fq,qBi,BFk->ki", {e.t[C3], e.t[T3b], Gr[x][1]});
   }
   // second projectors from the 2-column patch
@@ -422,19 +437,30 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
       const int xp = (x + 1) % Lx;
       const Site &m = env.at(x, y), &mp = env.at(xp, y), &n = env.at(x, yn), &np_ = env.at(xp, yn);
       const Ten &b = A.at(x, y), &bp = A.at(xp, y), &k = A.at(x, yn), &kp = A.at(xp, yn);
-      Ten rT = E.ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
-                      {C1t[x], m.t[T1b], n.t[T1k], C2t[x], T4kt[x], T4bt[x], b, k, T2kt[x], T2bt[x]});
-      Ten rB = E.ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
-                      {T4kt[xp], T4bt[xp], C4t[xp], mp.t[T3b], np_.t[T3k], C3t[xp], bp, kp, T2kt[xp], T2bt[xp]});
+      Ten rT, rB, sX, sZ, sT, sB;
       // the red upper half network factors through the (environment, D) bond
       // (h, S): rho_T = X^T Z, so M_red has rank <= chi_E D
-      Ten sX = E.ncon("ae,eWh,aSYP->YPWhS", {C1t[x], m.t[T1b], T4kt[x]});
-      Ten sZ = E.ncon("hci,ij,QcSKr,jrJ->hSKQJ", {n.t[T1k], C2t[x], k, T2kt[x]});
-      Ten sT = E.contract("YPWhS,hSKQJ->YPWKQJ", sX, sZ);
-      Ten sB = E.ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
-                      {T4bt[x], C4t[x], m.t[T3b], n.t[T3k], C3t[x], b, T2bt[x]});
+      if (alt) {
+        rT = E.ncon("ae,efh,hci,ij,aSY,YwGP,PfwBk,QcSKr,jrZQ,ZkF->GBKF",
+                    {C1t[x], m.t[T1b], n.t[T1k], C2t[x], T4kt[x], T4bt[x], b, k, T2kt[x], T2bt[x]});
+        rB = E.ncon("GSY,YwvP,vq,hoq,iXh,ni,PBwok,QKSXr,FrZQ,Zkn->GBKF",
+                    {T4kt[xp], T4bt[xp], C4t[xp], mp.t[T3b], np_.t[T3k], C3t[xp], bp, kp, T2kt[xp], T2bt[xp]});
+        sX = E.ncon("ae,eWh,aSY->YWhS", {C1t[x], m.t[T1b], T4kt[x]});
+        sZ = E.ncon("hci,ij,QcSKr,jrJQ->hSKJ", {n.t[T1k], C2t[x], k, T2kt[x]});
+        sT = E.contract("YWhS,hSKJ->YWKJ", sX, sZ);
+        sB = E.ncon("YwvP,vq,hoq,iKh,ni,PWwok,Jkn->YWKJ", {T4bt[x], C4t[x], m.t[T3b], n.t[T3k], C3t[x], b, T2bt[x]});
+      } else {
+        rT = E.ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
+                    {C1t[x], m.t[T1b], n.t[T1k], C2t[x], T4kt[x], T4bt[x], b, k, T2kt[x], T2bt[x]});
+        rB = E.ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
+                    {T4kt[xp], T4bt[xp], C4t[xp], mp.t[T3b], np_.t[T3k], C3t[xp], bp, kp, T2kt[xp], T2bt[xp]});
+        sX = E.ncon("ae,eWh,aSYP->YPWhS", {C1t[x], m.t[T1b], T4kt[x]});
+        sZ = E.ncon("hci,ij,QcSKr,jrJ->hSKQJ", {n.t[T1k], C2t[x], k, T2kt[x]});
+        sT = E.contract("YPWhS,hSKQJ->YPWKQJ", sX, sZ);
+        sB = E.ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ", {T4bt[x], C4t[x], m.t[T3b], n.t[T3k], C3t[x], b, T2bt[x]});
+      }
       rq.push_back({rT, rB, 2, true, ce, spectra ? &sTH[x] : nullptr});
-      rq.push_back({sT, sB, 3, true, ci, spectra ? &sR[x] : nullptr, sX, sZ});
+      rq.push_back({sT, sB, alt ? 2 : 3, true, ci, spectra ? &sR[x] : nullptr, sX, sZ});
     }
     auto out = E.projectors_batch(rq);
     for (int x = 0; x < Lx; ++x) {
@@ -460,8 +486,13 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
     const Ten& a = A.at(x, y);
     const int xu = (x - 1 + Lx) % Lx;
     nw[x].t[C1] = E.normalize(E.ncon("ge,efR,gfD->DR", {C1t[x], e.t[T1b], TH[xu][0]}));
-    nw[x].t[T4k] = E.normalize(E.ncon("gSYP,gWU,YPWD->DSU", {T4kt[x], TH[xu][1], R[x][0]}));
-    nw[x].t[T4b] = E.normalize(E.ncon("Ywg,PWwBs,YPWU,gBD->DsU", {T4bt[x], a, R[x][1], TH[x][0]}));
+    if (alt) {
+      nw[x].t[T4k] = E.normalize(E.ncon("gSY,gWU,YWD->DSU", {T4kt[x], TH[xu][1], R[x][0]}));
+      nw[x].t[T4b] = E.normalize(E.ncon("YwgP,PWwBs,YWU,gBD->DsU", {T4bt[x], a, R[x][1], TH[x][0]}));
+    } else {
+      nw[x].t[T4k] = E.normalize(E.ncon("gSYP,gWU,YPWD->DSU", {T4kt[x], TH[xu][1], R[x][0]}));
+      nw[x].t[T4b] = E.normalize(E.ncon("Ywg,PWwBs,YPWU,gBD->DsU", {T4bt[x], a, R[x][1], TH[x][0]}));
+    }
     nw[x].t[C4] = E.normalize(E.ncon("gq,Roq,goU->RU", {C4t[x], e.t[T3b], TH[x][1]}));
   }
   for (int x = 0; x < Lx; ++x) {
@@ -559,6 +590,7 @@ ctm_status validate(const ctm_config* cfg) {
   if (cfg->contract_prec < CTM_FP64 || cfg->contract_prec > CTM_BF16X6) return CTM_EINVAL;
   if (cfg->init != CTM_INIT_IDENTITY && cfg->init != CTM_INIT_PRODUCT) return CTM_EINVAL;
   if (cfg->init == CTM_INIT_IDENTITY && cfg->chi_I < cfg->D) return CTM_EINVAL;
+  if (cfg->projector_variant != CTM_PROJ_APP_A && cfg->projector_variant != CTM_PROJ_ALT_YR) return CTM_EINVAL;
   return CTM_OK;
 }
 
