@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--scaling-chi", type=int, default=170)
     ap.add_argument("--scaling-p", type=int, default=2)
     ap.add_argument("--scaling-prec", default="bf16x3")
+    ap.add_argument("--alt-yr", action="store_true",
+                    help="the alternative yellow / red projectors of App. B (physical leg cut by yellow) instead "
+                         "of those of App. A")
     return ap.parse_args()
 
 
@@ -150,7 +153,7 @@ def scaling(args) -> None:
     rows = []
     for D in [int(x) for x in args.scaling.split(",") if x]:
         A = torch.tensor(inp.peps_gaussian(700 + D, 1, 1, p, D), device="cuda:0")
-        obj = b.SplitCTM(A, chi, chi, prec=args.scaling_prec)
+        obj = b.SplitCTM(A, chi, chi, prec=args.scaling_prec, alt_yr=args.alt_yr)
         obj.sweep(2)
         torch.cuda.synchronize()
         n = 2
@@ -170,7 +173,8 @@ def scaling(args) -> None:
         y = np.log([t for _, t in pts])
         fit = float(np.polyfit(x, y, 1)[0])
     print(json.dumps({"scaling": rows, "chi_E": chi, "chi_I": chi, "p": p, "cell": "1x1",
-                      "prec": args.scaling_prec, "state": "seeded Gaussian", "exponent_fit_D_ge_6": fit}),
+                      "prec": args.scaling_prec, "state": "seeded Gaussian", "exponent_fit_D_ge_6": fit,
+                      "projectors": "App. B alternative yellow/red" if args.alt_yr else "App. A"}),
           flush=True)
 
 
@@ -206,7 +210,7 @@ def main():
     A = torch.tensor(inp.workload_peps(WORKLOAD), device=dev)
     h = inp.workload_h(WORKLOAD)
     obj = b.SplitCTM(A, chi, chi, prec=w["prec"], with_grad=True, n_sweeps=args.grad_sweeps,
-                     ckpt_every=args.ckpt)
+                     ckpt_every=args.ckpt, alt_yr=args.alt_yr)
 
     # untimed: converge the start environment (an optimisation step starts from
     # the previous step's environment)
@@ -277,7 +281,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "cell": "2x2", "p": 2, "D": 8, "chi_E": chi, "chi_I": chi,
                    "sweeps_per_eval": args.grad_sweeps, "ckpt_every": args.ckpt,
-                   "pre_sweeps": args.pre_sweeps},
+                   "pre_sweeps": args.pre_sweeps,
+                   "projectors": "App. B alternative yellow/red" if args.alt_yr else "App. A"},
         "sweeps_per_s": sweeps_per_s,
         "energy": e,
         "grad_norm": gnorm,
