@@ -16,9 +16,10 @@ Readings of the paper (it is silent or its figures are missing):
     yellow projectors inserted, as App. A requires), the bra layer of column
     y, the ket layer of column y+1 and the right environment after a
     bra-first half-step (green' / yellow' projectors: the same networks cut on
-    the other legs).  A 1-column patch leaves chi_E stuck at 1 from the
-    identity boundary, since every teal cut then carries a single environment
-    bond.  No figure of the paper fixes these networks, so they are pinned
+    the other legs).  A 1-column patch closed by the column's own right
+    environment leaves chi_E stuck at 1 from the identity boundary, since M
+    then spans that environment's single bond (the teal half projectors below
+    leave those legs open instead).  No figure of the paper fixes these networks, so they are pinned
     end to end only: Ising free energy and magnetisation against Onsager,
     product states, agreement with the conventional double-layer CTMRG as
     chi grows, a translation-invariant 2x2 cell equal to the 1x1 cell.
@@ -40,6 +41,16 @@ interlayer and D legs, so yellow truncates (chi_I, D, p) and M_yellow spans
 the remaining (D, chi_I) legs only.  The physical leg then rides on the
 intermediate T4^bra (and, mirrored, on T2^ket of the right environment) until
 the bra layer is absorbed, and red truncates (chi_I, D) only.
+
+Teal half projectors (App. B, the analogue of half projectors; flag
+half_teal; the figure constructionTealHalfProjectors has no body): the teal
+half networks keep only the left column of the 2-column patch, i.e. the left
+environment after the ket half-step with the bra layer of column y, for row
+x (rho^T) and row x+1 (rho^B).  Their legs towards the right (the T1^bra /
+T3^bra environment bond, the ket and the bra right legs) stay open instead of
+being closed by the right environment, so M_teal is (chi_E D^2)-dimensional
+with rank at most chi_E D.  (A 1-column patch closed by the right
+environment would keep chi_E at 1 from the identity boundary.)
 """
 from __future__ import annotations
 
@@ -286,13 +297,15 @@ def right_intermediate(env, A, Lx, y, Gr, Yr, alt_yr=False):
     return C2t, T2kt, T2bt, C3t
 
 
-def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, alt_yr=False):
+def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, alt_yr=False,
+                      half_teal=False):
     """Steps 1-3 of the left move of column y: green / yellow projectors,
     intermediate environments, teal / red projectors.  Returns
     (G, Y, TH, R, left intermediate env); G[x], TH[x] belong to the cut
     (x|x+1), Y[x], R[x] to row x; each is (P_T, P_B, S, k).  With alt_yr
     the teal networks carry the physical legs on the other intermediate
-    tensors, and red truncates (Y, W) of the networks below."""
+    tensors, and red truncates (Y, W) of the networks below.  With half_teal
+    the teal networks are the left halves (module docstring)."""
     yn = (y + 1) % Ly
     G, Y, Gr, Yr = _first_projectors(env, A, Lx, y, chi_E, chi_I, cutoff, adj_eps, alt_yr)
     if yn != y:
@@ -330,6 +343,13 @@ def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-
             sB = ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
                       T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
             n_red = 3
+        if half_teal:
+            if alt_yr:
+                rT = ncon("ae,efh,aSY,YwGP,PfwBk->GBhSk", C1t[x], m["T1b"], T4kt[x], T4bt[x], b)
+                rB = ncon("GSY,YwvP,vq,hoq,PBwok->GBhSk", T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], bp)
+            else:
+                rT = ncon("ae,efh,aSYP,YwG,PfwBk->GBhSk", C1t[x], m["T1b"], T4kt[x], T4bt[x], b)
+                rB = ncon("GSYP,Ywv,vq,hoq,PBwok->GBhSk", T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], bp)
         TH[x] = projectors(rT, rB, 2, chi_E, cutoff, adj_eps)
         R[x] = projectors(sT, sB, n_red, chi_I, cutoff, adj_eps)
     return G, Y, TH, R, (C1t, T4kt, T4bt, C4t)
@@ -337,16 +357,16 @@ def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-
 
 def left_move(env: Dict, A: Dict, Lx: int, Ly: int, chi_E: int, chi_I: int,
               cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None,
-              alt_yr: bool = False):
+              alt_yr: bool = False, half_teal: bool = False):
     """Absorb every column of the cell into the left environment, in place,
     one column after the other (left_move_column)."""
     for y in range(Ly):
-        left_move_column(env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps, info, alt_yr)
+        left_move_column(env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps, info, alt_yr, half_teal)
 
 
 def left_move_column(env: Dict, A: Dict, Lx: int, Ly: int, y: int, chi_E: int, chi_I: int,
                      cutoff: float = 1e-12, adj_eps: float = 1e-12, info: dict | None = None,
-                     alt_yr: bool = False):
+                     alt_yr: bool = False, half_teal: bool = False):
     """Absorb column y into the left environment of column y+1, in place.
 
     Every row x:
@@ -360,11 +380,11 @@ def left_move_column(env: Dict, A: Dict, Lx: int, Ly: int, y: int, chi_E: int, c
          (App. A: these half networks contain the first projectors; the b
          legs are (D, chi_E) for teal and (D, p, chi_I) for red);
       4. bra half-step: new C1, T4k, T4b, C4 of site [x, y+1], normalised.
-    alt_yr: the alternative yellow / red projectors of App. B (module
-    docstring)."""
+    alt_yr, half_teal: the alternative yellow / red projectors and the teal
+    half projectors of App. B (module docstring)."""
     yn = (y + 1) % Ly
     G, Y, TH, R, (C1t, T4kt, T4bt, C4t) = column_projectors(
-        env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps, alt_yr)
+        env, A, Lx, Ly, y, chi_E, chi_I, cutoff, adj_eps, alt_yr, half_teal)
     new = {}
     for x in range(Lx):
         e, a = env[(x, y)], A[(x, y)]
@@ -463,9 +483,9 @@ def from_frame(direction: str, env, A, Lx, Ly):
 
 
 def move(direction: str, env, A, Lx, Ly, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, info=None,
-         alt_yr=False):
+         alt_yr=False, half_teal=False):
     e2, a2, lx, ly = to_frame(direction, env, A, Lx, Ly)
-    left_move(e2, a2, lx, ly, chi_E, chi_I, cutoff, adj_eps, info, alt_yr)
+    left_move(e2, a2, lx, ly, chi_E, chi_I, cutoff, adj_eps, info, alt_yr, half_teal)
     e3, _, _, _ = from_frame(direction, e2, a2, lx, ly)
     return e3
 
@@ -496,21 +516,22 @@ def spectra_delta(s_old, s_new) -> float:
     return d
 
 
-def sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, info=None, alt_yr=False):
+def sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, info=None, alt_yr=False,
+          half_teal=False):
     """One directional split-CTMRG step: left, top, right and bottom moves."""
     for direction in ("left", "top", "right", "bottom"):
-        env = move(direction, env, A, Lx, Ly, chi_E, chi_I, cutoff, adj_eps, info, alt_yr)
+        env = move(direction, env, A, Lx, Ly, chi_E, chi_I, cutoff, adj_eps, info, alt_yr, half_teal)
     return env
 
 
-def run(env, A, Lx, Ly, chi_E, chi_I, max_sweeps, tol=0.0, cutoff=1e-12, alt_yr=False):
+def run(env, A, Lx, Ly, chi_E, chi_I, max_sweeps, tol=0.0, cutoff=1e-12, alt_yr=False, half_teal=False):
     """Iterate sweeps until the corner spectra change by less than tol.
     Returns (env, sweeps_done, delta)."""
     s_old = corner_spectra(env)
     delta = math.inf
     done = 0
     for _ in range(max_sweeps):
-        env = sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff, alt_yr=alt_yr)
+        env = sweep(env, A, Lx, Ly, chi_E, chi_I, cutoff, alt_yr=alt_yr, half_teal=half_teal)
         done += 1
         s_new = corner_spectra(env)
         delta = spectra_delta(s_old, s_new)

@@ -249,15 +249,15 @@ def test_direction_maps_on_c4v_symmetric_state():
 # ---------------------------------------------------------------------------
 # whole CTMRG: closed forms
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("alt_yr", [False, True])
+@pytest.mark.parametrize("alt_yr,half_teal", [(False, False), (True, False), (False, True), (True, True)])
 @pytest.mark.parametrize("D", [1, 2])
-def test_product_states_exact_energy(D, alt_yr):
+def test_product_states_exact_energy(D, alt_yr, half_teal):
     """Rank-1 virtual structure: the state is a product of identical real
     spinors; each bond gives +1/4 for S.S and -1/4 in the rotated frame
-    (with either yellow / red construction)."""
+    (with every projector construction)."""
     A = sc.peps_from_numpy(inp.peps_product(3 + D, 2, D))
     env = sc.init_identity(1, 1, D)
-    env, _, _ = sc.run(env, A, 1, 1, 6, 6, 4, alt_yr=alt_yr)
+    env, _, _ = sc.run(env, A, 1, 1, 6, 6, 4, alt_yr=alt_yr, half_teal=half_teal)
     e, _ = sc.energy(env, A, 1, 1, inp.heisenberg_h())
     e2, _ = sc.energy(env, A, 1, 1, inp.heisenberg_h_rotated())
     assert abs(float(e) - 0.5) < 1e-12
@@ -301,13 +301,14 @@ def test_honeycomb_coarse_grained_product_state_energy():
     assert abs(eh_sw - float(bonds[(0, 0)][0])) > 0.1
 
 
-@pytest.mark.parametrize("beta,alt_yr", [(0.3, False), (0.6, False), (0.3, True)])
-def test_ising_free_energy_and_correlator(beta, alt_yr):
+@pytest.mark.parametrize("beta,alt_yr,half_teal", [(0.3, False, False), (0.6, False, False), (0.3, True, False),
+                                                   (0.3, True, True)])
+def test_ising_free_energy_and_correlator(beta, alt_yr, half_teal):
     """Square-root Boltzmann PEPS: <psi|psi> = Z_Ising, so the per-site log
     partition function and the nearest-neighbour correlator are Onsager's."""
     A = sc.peps_from_numpy(inp.peps_ising(beta))
     env = sc.init_identity(1, 1, 2)
-    env, _, _ = sc.run(env, A, 1, 1, 16, 16, 60, alt_yr=alt_yr)
+    env, _, _ = sc.run(env, A, 1, 1, 16, 16, 60, alt_yr=alt_yr, half_teal=half_teal)
     lk = float(sc.log_kappa(env[(0, 0)], A[(0, 0)]))
     _, b = sc.energy(env, A, 1, 1, inp.sz_sz())
     eh, ev = (float(t) for t in b[(0, 0)])
@@ -380,11 +381,14 @@ def test_split_converges_to_conventional_as_chi_grows():
 
 
 @pytest.mark.slow
-def test_alternative_yellow_red_converges_to_conventional_as_chi_grows():
+@pytest.mark.parametrize("alt_yr,half_teal", [(True, False), (False, True), (True, True)])
+def test_app_b_constructions_converge_to_conventional_as_chi_grows(alt_yr, half_teal):
     """App. B: with the physical leg cut by the yellow projectors (which then
-    compress (chi_I, D, p) through the (D, chi_I) legs of M_yellow) the split
-    CTMRG still reaches the conventional fixed point as chi = chi_E = chi_I
-    grows; a wrong leg in any of its networks breaks this."""
+    compress (chi_I, D, p) through the (D, chi_I) legs of M_yellow), with the
+    teal half projectors (left halves of the patch, right legs open), or both,
+    the split CTMRG still reaches the conventional fixed point as
+    chi = chi_E = chi_I grows (chi_E grows from the identity boundary); a wrong
+    leg in any of their networks breaks this."""
     A_np = inp.peps_gaussian(7, 1, 1, 2, 2)
     h = inp.heisenberg_h_rotated()
     env_c, Ad = cc.run(A_np, 16, 40)
@@ -393,7 +397,8 @@ def test_alternative_yellow_red_converges_to_conventional_as_chi_grows():
     diffs = []
     for chi in (4, 8, 16):
         env = sc.init_identity(1, 1, 2)
-        env, _, _ = sc.run(env, A, 1, 1, chi, chi, 40, alt_yr=True)
+        env, _, _ = sc.run(env, A, 1, 1, chi, chi, 40, alt_yr=alt_yr, half_teal=half_teal)
+        assert min(env[(0, 0)]["C1"].shape) >= min(chi, 8)   # chi_E grew (up to the 1e-12 cutoff)
         es, _ = sc.energy(env, A, 1, 1, h)
         diffs.append(abs(float(es) - e_ref) / abs(e_ref))
     assert diffs[0] > diffs[1] > diffs[2]
@@ -445,19 +450,20 @@ def test_gradient_matches_finite_differences_and_scale_invariance():
         assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3 * np.linalg.norm(g)), (fd, an)
 
 
-def test_alternative_construction_gradient_matches_finite_differences():
-    """Reverse mode through the App. B construction (two sweeps from the
+@pytest.mark.parametrize("alt_yr,half_teal", [(True, False), (True, True)])
+def test_alternative_construction_gradient_matches_finite_differences(alt_yr, half_teal):
+    """Reverse mode through the App. B constructions (two sweeps from the
     fixed random start of the test above) against a fourth-order central
     difference."""
     A = inp.peps_gaussian(11, 1, 1, 2, 2)
     chi, ns = 4, 2
     env0 = inp.random_env(5, 1, 1, 2, chi, chi)
     h = inp.heisenberg_h_rotated()
-    e, g = og.energy_and_grad(A, env0, chi, chi, ns, h, alt_yr=True)
+    e, g = og.energy_and_grad(A, env0, chi, chi, ns, h, alt_yr=alt_yr, half_teal=half_teal)
     assert abs(float((A * g).sum())) < 1e-10 * np.linalg.norm(A) * np.linalg.norm(g)
     rng = np.random.default_rng(1)
     for d in [rng.standard_normal(A.shape) for _ in range(2)]:
-        fd = og.central_difference4(A, env0, chi, chi, ns, h, d, step=1e-5, alt_yr=True)
+        fd = og.central_difference4(A, env0, chi, chi, ns, h, d, step=1e-5, alt_yr=alt_yr, half_teal=half_teal)
         an = float((g * d).sum())
         assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3 * np.linalg.norm(g)), (fd, an)
 
