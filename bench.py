@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--alt-yr", action="store_true",
                     help="the alternative yellow / red projectors of App. B (physical leg cut by yellow) instead "
                          "of those of App. A")
+    ap.add_argument("--half-teal", action="store_true",
+                    help="the teal half projectors of App. B (left halves of the patch) instead of the full ones")
     return ap.parse_args()
 
 
@@ -140,6 +142,15 @@ def cpu_baseline(threads: int) -> dict:
                       f"{dt:.1f} s, scaled x{4 * w['Ly']} to one sweep"}
 
 
+def projectors_label(args) -> str:
+    parts = []
+    if args.alt_yr:
+        parts.append("App. B alternative yellow/red")
+    if args.half_teal:
+        parts.append("App. B teal half projectors")
+    return ", ".join(parts) if parts else "App. A"
+
+
 def scaling(args) -> None:
     """Time of one sweep (four directional moves, each absorbing the ket and
     bra layers of every column) against the bulk bond dimension D at fixed
@@ -153,7 +164,7 @@ def scaling(args) -> None:
     rows = []
     for D in [int(x) for x in args.scaling.split(",") if x]:
         A = torch.tensor(inp.peps_gaussian(700 + D, 1, 1, p, D), device="cuda:0")
-        obj = b.SplitCTM(A, chi, chi, prec=args.scaling_prec, alt_yr=args.alt_yr)
+        obj = b.SplitCTM(A, chi, chi, prec=args.scaling_prec, alt_yr=args.alt_yr, half_teal=args.half_teal)
         obj.sweep(2)
         torch.cuda.synchronize()
         n = 2
@@ -174,7 +185,7 @@ def scaling(args) -> None:
         fit = float(np.polyfit(x, y, 1)[0])
     print(json.dumps({"scaling": rows, "chi_E": chi, "chi_I": chi, "p": p, "cell": "1x1",
                       "prec": args.scaling_prec, "state": "seeded Gaussian", "exponent_fit_D_ge_6": fit,
-                      "projectors": "App. B alternative yellow/red" if args.alt_yr else "App. A"}),
+                      "projectors": projectors_label(args)}),
           flush=True)
 
 
@@ -210,7 +221,7 @@ def main():
     A = torch.tensor(inp.workload_peps(WORKLOAD), device=dev)
     h = inp.workload_h(WORKLOAD)
     obj = b.SplitCTM(A, chi, chi, prec=w["prec"], with_grad=True, n_sweeps=args.grad_sweeps,
-                     ckpt_every=args.ckpt, alt_yr=args.alt_yr)
+                     ckpt_every=args.ckpt, alt_yr=args.alt_yr, half_teal=args.half_teal)
 
     # untimed: converge the start environment (an optimisation step starts from
     # the previous step's environment)
@@ -282,7 +293,7 @@ def main():
         "config": {"workload": WORKLOAD, "cell": "2x2", "p": 2, "D": 8, "chi_E": chi, "chi_I": chi,
                    "sweeps_per_eval": args.grad_sweeps, "ckpt_every": args.ckpt,
                    "pre_sweeps": args.pre_sweeps,
-                   "projectors": "App. B alternative yellow/red" if args.alt_yr else "App. A"},
+                   "projectors": projectors_label(args)},
         "sweeps_per_s": sweeps_per_s,
         "energy": e,
         "grad_norm": gnorm,

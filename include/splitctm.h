@@ -70,15 +70,18 @@ typedef enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16X3 = 2, CTM_BF16X6 = 3 } ctm_
  * passed in with ctm_env_import. */
 typedef enum { CTM_INIT_IDENTITY = 0, CTM_INIT_PRODUCT = 1 } ctm_init_mode;
 
-/* Yellow / red projector construction.  APP_A: the networks of App. A
- * (Figs. constructionYellowProjectors, constructionRedProjectors): yellow
- * truncates (chi_I, D), red truncates (chi_I, p, D).  ALT_YR: the alternative
- * of App. B (Figs. alternativeConstructionYellowProjectors,
- * alternativeConstructionRedProjectors): the same yellow networks, but the
- * physical leg is cut together with (chi_I, D), so M_yellow spans only the
- * (D, chi_I) legs, and red truncates (chi_I, D); no SVD then carries the p
- * factor. */
-typedef enum { CTM_PROJ_APP_A = 0, CTM_PROJ_ALT_YR = 1 } ctm_projector_variant;
+/* Projector constructions (bit flags).  APP_A (0): the networks of App. A.
+ * ALT_YR: the alternative yellow / red projectors of App. B (Figs.
+ * alternativeConstructionYellowProjectors, alternativeConstructionRedProjectors):
+ * the yellow networks of App. A, but the physical leg is cut together with
+ * (chi_I, D), so M_yellow spans only the (D, chi_I) legs, and red truncates
+ * (chi_I, D); no SVD then carries the p factor.  HALF_TEAL: the teal half
+ * projectors of App. B (the analogue of half projectors; the paper's network
+ * figure has no body): the teal half networks are the left column of the
+ * 2-column patch, with their legs towards the right left open, so M_teal is
+ * chi_E D^2-dimensional with rank <= chi_E D (chi_E D^2 <= 8192).  The two
+ * flags combine. */
+typedef enum { CTM_PROJ_APP_A = 0, CTM_PROJ_ALT_YR = 1, CTM_PROJ_HALF_TEAL = 2 } ctm_projector_variant;
 
 typedef struct {
   int Lx, Ly;                  /* unit cell: rows, columns */
@@ -88,7 +91,7 @@ typedef struct {
   double svd_rel_cutoff;       /* drop singular values below cutoff * s_1 (<= 0: 1e-12) */
   double svd_adj_eps;          /* Lorentzian broadening of the SVD adjoint (<= 0: 1e-12) */
   ctm_init_mode init;
-  ctm_projector_variant projector_variant;
+  int projector_variant;       /* ctm_projector_variant flags */
 } ctm_config;
 
 typedef struct ctm_ctx ctm_ctx;

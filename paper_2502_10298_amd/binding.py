@@ -92,9 +92,11 @@ def strerror(status: int) -> str:
 
 
 def make_config(Lx, Ly, p, D, chi_E, chi_I, prec="fp64", init="identity", cutoff=1e-12, adj_eps=1e-12,
-                alt_yr=False):
-    """alt_yr: the alternative yellow / red projectors of App. B."""
-    return ctm_config(Lx, Ly, p, D, chi_E, chi_I, PREC[prec], cutoff, adj_eps, INIT[init], 1 if alt_yr else 0)
+                alt_yr=False, half_teal=False):
+    """alt_yr / half_teal: the alternative yellow / red projectors and the
+    teal half projectors of App. B (they combine)."""
+    return ctm_config(Lx, Ly, p, D, chi_E, chi_I, PREC[prec], cutoff, adj_eps, INIT[init],
+                      (1 if alt_yr else 0) | (2 if half_teal else 0))
 
 
 def workspace_size(cfg: ctm_config, with_grad=False, n_sweeps=0, ckpt_every=1) -> int:
@@ -118,18 +120,19 @@ class SplitCTM:
     """One split-CTMRG context on the current HIP device.
 
     A: torch FP64 tensor [Lx, Ly, p, D, D, D, D] on the GPU (copied at init).
-    alt_yr: the alternative yellow / red projectors of App. B."""
+    alt_yr / half_teal: the alternative yellow / red projectors and the teal
+    half projectors of App. B."""
 
     def __init__(self, A, chi_E, chi_I=None, prec="fp64", init="identity", boundary=None,
                  with_grad=False, n_sweeps=0, ckpt_every=1, cutoff=1e-12, adj_eps=1e-12,
-                 workspace_bytes=None, stream=None, alt_yr=False):
+                 workspace_bytes=None, stream=None, alt_yr=False, half_teal=False):
         import torch
         self.torch = torch
         if A.dtype != torch.float64 or not A.is_cuda or A.dim() != 7:
             raise ValueError("A must be a CUDA float64 tensor [Lx, Ly, p, D, D, D, D]")
         Lx, Ly, p, D = A.shape[:4]
         self.cfg = make_config(Lx, Ly, p, D, chi_E, chi_I if chi_I is not None else chi_E, prec, init,
-                               cutoff, adj_eps, alt_yr)
+                               cutoff, adj_eps, alt_yr, half_teal)
         need = workspace_size(self.cfg, with_grad, n_sweeps, ckpt_every)
         self.ws_bytes = int(workspace_bytes) if workspace_bytes is not None else need
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=A.device)
@@ -189,7 +192,7 @@ class SplitCTM:
         if st != CTM_OK:
             raise CtmError(st, "ctm_projectors")
         c = self.cfg
-        if c.projector_variant == 1:   # App. B: the physical leg is cut by yellow
+        if c.projector_variant & 1:   # App. B: the physical leg is cut by yellow
             shapes = [(c.chi_E, c.D, c.chi_E)] * 4 + [(c.chi_I, c.D, c.p, c.chi_I)] * 2 + [(c.chi_I, c.D, c.chi_I)] * 2
         else:
             shapes = [(c.chi_E, c.D, c.chi_E)] * 4 + [(c.chi_I, c.D, c.chi_I)] * 2 + [(c.chi_I, c.p, c.D, c.chi_I)] * 2

@@ -347,7 +347,12 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
   // App. B alternative: yellow (yellow') also cuts the ket (bra) physical
   // leg, which then rides on T4bt (T2kt) until the other layer is absorbed,
   // and red truncates (chi_I, D) only
-  const bool alt = c.cfg.projector_variant == CTM_PROJ_ALT_YR;
+  const bool alt = (c.cfg.projector_variant & CTM_PROJ_ALT_YR) != 0;
+  // App. B teal half projectors: the teal networks are the left column of
+  // the patch (left environment after the ket half-step, bra of column y),
+  // their legs towards the right (T1b / T3b environment bond, ket and bra
+  // right legs) left open
+  const bool half = (c.cfg.projector_variant & CTM_PROJ_HALF_TEAL) != 0;
   const int ny = alt ? 3 : 2;
   std::vector<Ten> gT(Lx), gB(Lx), yT(Lx), yB(Lx), gT2, gB2, yT2, yB2;
   for (int x = 0; x < Lx; ++x) {
@@ -458,6 +463,15 @@ void left_column(ctm_ctx& c, Env& env, const Peps& A, int y, Column* col, int wa
         sZ = E.ncon("hci,ij,QcSKr,jrJ->hSKQJ", {n.t[T1k], C2t[x], k, T2kt[x]});
         sT = E.contract("YPWhS,hSKQJ->YPWKQJ", sX, sZ);
         sB = E.ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ", {T4bt[x], C4t[x], m.t[T3b], n.t[T3k], C3t[x], b, T2bt[x]});
+      }
+      if (half) {
+        if (alt) {
+          rT = E.ncon("ae,efh,aSY,YwGP,PfwBk->GBhSk", {C1t[x], m.t[T1b], T4kt[x], T4bt[x], b});
+          rB = E.ncon("GSY,YwvP,vq,hoq,PBwok->GBhSk", {T4kt[xp], T4bt[xp], C4t[xp], mp.t[T3b], bp});
+        } else {
+          rT = E.ncon("ae,efh,aSYP,YwG,PfwBk->GBhSk", {C1t[x], m.t[T1b], T4kt[x], T4bt[x], b});
+          rB = E.ncon("GSYP,Ywv,vq,hoq,PBwok->GBhSk", {T4kt[xp], T4bt[xp], C4t[xp], mp.t[T3b], bp});
+        }
       }
       rq.push_back({rT, rB, 2, true, ce, spectra ? &sTH[x] : nullptr});
       rq.push_back({sT, sB, alt ? 2 : 3, true, ci, spectra ? &sR[x] : nullptr, sX, sZ});
@@ -590,7 +604,18 @@ ctm_status validate(const ctm_config* cfg) {
   if (cfg->contract_prec < CTM_FP64 || cfg->contract_prec > CTM_BF16X6) return CTM_EINVAL;
   if (cfg->init != CTM_INIT_IDENTITY && cfg->init != CTM_INIT_PRODUCT) return CTM_EINVAL;
   if (cfg->init == CTM_INIT_IDENTITY && cfg->chi_I < cfg->D) return CTM_EINVAL;
-  if (cfg->projector_variant != CTM_PROJ_APP_A && cfg->projector_variant != CTM_PROJ_ALT_YR) return CTM_EINVAL;
+  if (cfg->projector_variant < 0 || cfg->projector_variant > (CTM_PROJ_ALT_YR | CTM_PROJ_HALF_TEAL)) return CTM_EINVAL;
+  // every projector matrix M (n_b x n_b, rank <= r0 when r0 < n_b) must fit
+  // the SVD: the Jacobi takes n <= 4096, the rank-limited route's
+  // Householder QR n_b <= 8192 rows
+  const long ce = cfg->chi_E, ci = cfg->chi_I, D = cfg->D, p = cfg->p;
+  const bool alt = (cfg->projector_variant & CTM_PROJ_ALT_YR) != 0;
+  const bool half = (cfg->projector_variant & CTM_PROJ_HALF_TEAL) != 0;
+  auto fits = [](long nb, long r0) { return nb <= 4096 || (r0 > 0 && r0 < nb && r0 <= 4096 && nb <= 8192); };
+  if (!fits(ce * D, 0)) return CTM_EINVAL;                                        // green, green'
+  if (!fits(half ? ce * D * D : ce * D, half ? ce * D : 0)) return CTM_EINVAL;    // teal
+  if (!fits(alt ? ci * D : ci * p * D, alt ? 0 : ci * D)) return CTM_EINVAL;      // yellow, yellow'
+  if (!fits(alt ? ci * D : ci * p * D, ce * D)) return CTM_EINVAL;                // red
   return CTM_OK;
 }
 

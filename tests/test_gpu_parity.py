@@ -443,48 +443,65 @@ def test_gradient_parity_chiI_below_chiE_fp64():
 
 
 # ---------------------------------------------------------------------------
-# App. B alternative yellow / red projectors (physical leg cut by yellow)
+# App. B constructions: alternative yellow / red projectors (physical leg cut
+# by yellow) and teal half projectors (left halves of the patch), alone and
+# combined
 # ---------------------------------------------------------------------------
-def test_alt_yr_energy_parity_fp64():
-    """D=2, chi=8, 20 sweeps from the identity boundary with the alternative
-    yellow / red construction: GPU FP64 equals the oracle to 1e-10."""
+APP_B = [(True, False), (False, True), (True, True)]
+
+
+def _oracle_run_v(A_np, chi, sweeps, alt_yr, half_teal):
+    Lx, Ly = A_np.shape[:2]
+    A = sc.peps_from_numpy(A_np)
+    env = sc.init_identity(Lx, Ly, A_np.shape[3])
+    for _ in range(sweeps):
+        env = sc.sweep(env, A, Lx, Ly, chi, chi, alt_yr=alt_yr, half_teal=half_teal)
+    return env, A
+
+
+@pytest.mark.parametrize("alt_yr,half_teal", APP_B)
+def test_app_b_energy_parity_fp64(alt_yr, half_teal):
+    """D=2, chi=8, 20 sweeps from the identity boundary with the App. B
+    constructions: GPU FP64 equals the oracle to 1e-10."""
     A_np = inp.workload_peps("d2_D2_chi8")
     h = inp.heisenberg_h_rotated()
-    _say("alt_yr energy d2_D2_chi8 fp64")
-    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 8, prec="fp64", alt_yr=True)
+    _say("app_b energy d2_D2_chi8 fp64", alt_yr, half_teal)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 8, prec="fp64", alt_yr=alt_yr, half_teal=half_teal)
     obj.sweep(20)
     e_gpu, bonds = obj.energy(h)
-    env, A = _oracle_run(A_np, 8, 20, alt_yr=True)
+    env, A = _oracle_run_v(A_np, 8, 20, alt_yr, half_teal)
     e_ref, bref = sc.energy(env, A, 1, 1, h)
     assert abs(e_gpu - float(e_ref)) <= 1e-10 * abs(float(e_ref)), (e_gpu, float(e_ref))
     assert abs(bonds[0, 0, 0] - float(bref[(0, 0)][0])) <= 1e-10
     assert abs(bonds[0, 0, 1] - float(bref[(0, 0)][1])) <= 1e-10
 
 
-def test_alt_yr_cell_2x2_parity_fp64():
-    """2x2 cell of four different tensors (D=2, chi=6), alternative yellow /
-    red construction: every bond energy."""
+@pytest.mark.parametrize("alt_yr,half_teal", APP_B)
+def test_app_b_cell_2x2_parity_fp64(alt_yr, half_teal):
+    """2x2 cell of four different tensors (D=2, chi=6), App. B constructions:
+    every bond energy."""
     A_np = inp.peps_gaussian(91, 2, 2, 2, 2)
     h = inp.heisenberg_h()
-    _say("alt_yr cell2x2 d2 chi6 fp64")
-    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 6, prec="fp64", alt_yr=True)
+    _say("app_b cell2x2 d2 chi6 fp64", alt_yr, half_teal)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 6, prec="fp64", alt_yr=alt_yr, half_teal=half_teal)
     obj.sweep(4)
     e_gpu, bonds = obj.energy(h)
-    env, A = _oracle_run(A_np, 6, 4, alt_yr=True)
+    env, A = _oracle_run_v(A_np, 6, 4, alt_yr, half_teal)
     e_ref, bref = sc.energy(env, A, 2, 2, h)
     assert abs(e_gpu - float(e_ref)) <= 1e-10 * abs(float(e_ref))
     for (x, y), (eh, ev) in bref.items():
         assert abs(bonds[x, y, 0] - float(eh)) <= 1e-9 and abs(bonds[x, y, 1] - float(ev)) <= 1e-9
 
 
-def test_alt_yr_projectors_parity_fp64():
-    """The four projector pairs of every direction (yellow [chi_I, D, p,
-    chi_I], red [chi_I, D, chi_I]) agree with the oracle's from the same
-    environment."""
+@pytest.mark.parametrize("alt_yr,half_teal", APP_B)
+def test_app_b_projectors_parity_fp64(alt_yr, half_teal):
+    """The four projector pairs of every direction (with ALT_YR: yellow
+    [chi_I, D, p, chi_I], red [chi_I, D, chi_I]) agree with the oracle's from
+    the same environment."""
     A_np = inp.peps_gaussian(77, 1, 1, 2, 2)
     chi = 6
-    _say("alt_yr projectors d2 chi6")
-    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec="fp64", alt_yr=True)
+    _say("app_b projectors d2 chi6", alt_yr, half_teal)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec="fp64", alt_yr=alt_yr, half_teal=half_teal)
     obj.sweep(3)
     flat = obj.env_export().cpu().numpy()
     env = sc.env_from_numpy(inp.unpack_env(flat, 1, 1, 2, chi, chi))
@@ -492,8 +509,9 @@ def test_alt_yr_projectors_parity_fp64():
     for direction in range(4):
         P, te = obj.projectors(direction, 0, 0)
         e2, a2, lx, ly = sc.to_frame(["left", "top", "right", "bottom"][direction], env, A, 1, 1)
-        G, Y, TH, R, _ = sc.column_projectors(e2, a2, lx, ly, 0, chi, chi, alt_yr=True)
-        assert Y[0][0].shape[:3] == (chi, 2, 2) and R[0][0].dim() == 3
+        G, Y, TH, R, _ = sc.column_projectors(e2, a2, lx, ly, 0, chi, chi, alt_yr=alt_yr, half_teal=half_teal)
+        if alt_yr:
+            assert Y[0][0].shape[:3] == (chi, 2, 2) and R[0][0].dim() == 3
         for nm, pr in (("green", G[0]), ("teal", TH[0]), ("yellow", Y[0]), ("red", R[0])):
             k = pr[3]
             for j, side in ((0, "_T"), (1, "_B")):
@@ -504,19 +522,20 @@ def test_alt_yr_projectors_parity_fp64():
                 assert torch.allclose(got, ref, atol=1e-8 * scale, rtol=0), (direction, nm, side)
 
 
-def test_alt_yr_gradient_parity_fp64():
-    """dE/dA through the alternative construction (hand-written adjoints)
-    equals the oracle's autograd gradient (2 sweeps from a random start)."""
+@pytest.mark.parametrize("alt_yr,half_teal", APP_B)
+def test_app_b_gradient_parity_fp64(alt_yr, half_teal):
+    """dE/dA through the App. B constructions (hand-written adjoints) equals
+    the oracle's autograd gradient (2 sweeps from a random start)."""
     A_np = inp.peps_gaussian(11, 1, 1, 2, 2)
     chi, ns = 4, 2
     env0 = inp.random_env(5, 1, 1, 2, chi, chi)
     h = inp.heisenberg_h_rotated()
-    _say("alt_yr gradient d2 chi4 fp64")
+    _say("app_b gradient d2 chi4 fp64", alt_yr, half_teal)
     obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec="fp64", with_grad=True, n_sweeps=ns, ckpt_every=1,
-                     alt_yr=True)
+                     alt_yr=alt_yr, half_teal=half_teal)
     obj.env_import(torch.tensor(inp.pack_env(env0, 1, 1, 2, chi, chi), device=DEV))
     e_gpu, dA = obj.energy_grad(h, ns, 1)
-    e_ref, g_ref = og.energy_and_grad(A_np, env0, chi, chi, ns, h, alt_yr=True)
+    e_ref, g_ref = og.energy_and_grad(A_np, env0, chi, chi, ns, h, alt_yr=alt_yr, half_teal=half_teal)
     assert abs(e_gpu - e_ref) <= 1e-10 * abs(e_ref)
     g = dA.cpu().numpy()
     assert np.linalg.norm(g - g_ref) <= 1e-8 * np.linalg.norm(g_ref)
