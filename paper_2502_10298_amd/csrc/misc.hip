@@ -4,6 +4,9 @@
 // projector truncation / sign fix, and the bond-energy ratio.
 #include "kernels.hpp"
 
+#include <cstdint>
+#include <type_traits>
+
 namespace sctm {
 
 static constexpr int RED_BLOCKS = 1024;
@@ -171,6 +174,27 @@ static void launch_permute32(hipStream_t s, const void* in, void* out, const Per
     }
     dim3 g((t.DX + 31) / 32, (t.DY + 31) / 32, t.nr < 65535u ? t.nr : 65535u);
     hipLaunchKernelGGL(permute_tiled_kernel<T>, g, dim3(32, 8), 0, s, (const T*)in, (T*)out, t, acc);
+    return;
+  }
+  // innermost output axis also innermost in the input (contiguous runs of
+  // its length in both): the runs move as 16-byte vectors, every other
+  // input stride being a multiple of the run length
+  constexpr int VW = 16 / (int)sizeof(T);
+  bool vec_ok = yax == d.rank - 1 && d.out_dims[d.rank - 1] % VW == 0 && ((uintptr_t)in | (uintptr_t)out) % 16 == 0;
+  for (int i = 0; i + 1 < d.rank && vec_ok; ++i)
+    if (d.out_dims[i] > 1 && d.in_strides_perm[i] % VW != 0) vec_ok = false;
+  if (vec_ok) {
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    PermGeneric gv;
+    gv.rank = d.rank;
+    for (int i = 0; i < d.rank; ++i) {
+      const bool inner = i == d.rank - 1;
+      gv.dv[i] = make_fastdiv((unsigned)(inner ? d.out_dims[i] / VW : d.out_dims[i]));
+      gv.istr[i] = inner ? 1u : (unsigned)(d.in_strides_perm[i] / VW);
+    }
+    const long nv = n / VW;
+    hipLaunchKernelGGL(permute32_kernel<V>, dim3(grid_for(nv)), dim3(256), 0, s, (const V*)in, (V*)out, gv,
+                       (unsigned)nv, acc);
     return;
   }
   PermGeneric gd;
