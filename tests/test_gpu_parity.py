@@ -539,3 +539,23 @@ def test_app_b_gradient_parity_fp64(alt_yr, half_teal):
     assert abs(e_gpu - e_ref) <= 1e-10 * abs(e_ref)
     g = dA.cpu().numpy()
     assert np.linalg.norm(g - g_ref) <= 1e-8 * np.linalg.norm(g_ref)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 5e-6), ("bf16x6", 1e-6), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("alt_yr,half_teal", APP_B)
+def test_app_b_mixed_precision_energy(prec, tol, alt_yr, half_teal):
+    """The App. B constructions with reduced-precision contractions (FP64
+    projectors) against the FP64 oracle of the same construction.  Measured
+    relative energy errors (alt / half / both): FP32 1.9e-6 / 1.8e-7 / 2.0e-7,
+    BF16x6 2.4e-7 / 2.9e-7 / 1.5e-7, BF16x3 5.8e-6 / 5.2e-6 / 7.5e-6; the
+    alternative yellow / red is the most sensitive to FP32 rounding, hence
+    the FP32 bound of 5e-6 (1e-6 for App. A)."""
+    A_np = inp.workload_peps("d2_D2_chi8")
+    h = inp.heisenberg_h_rotated()
+    _say("app_b energy d2_D2_chi8", prec, alt_yr, half_teal)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 8, prec=prec, alt_yr=alt_yr, half_teal=half_teal)
+    obj.sweep(30)
+    e_gpu, _ = obj.energy(h)
+    env, A = _oracle_run_v(A_np, 8, 30, alt_yr, half_teal)
+    e_ref, _ = sc.energy(env, A, 1, 1, h)
+    assert abs(e_gpu - float(e_ref)) <= tol * abs(float(e_ref)), (e_gpu, float(e_ref))

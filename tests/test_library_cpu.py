@@ -60,3 +60,19 @@ def test_debug_decompositions_reject_sizes_beyond_their_limits():
     assert L.ctm_debug_svd(0, 1, d, d, d, d, d, ctypes.byref(sw), None) == b.CTM_EINVAL
     assert L.ctm_debug_qr(8193, 16, 1, d, d, d, d, None) == b.CTM_EINVAL
     assert L.ctm_debug_qr(16, 17, 1, d, d, d, d, None) == b.CTM_EINVAL   # k > m
+
+
+def test_projector_variants_and_svd_limits_validated():
+    """Every projector construction plans at the headline size; a teal half
+    projector matrix beyond the rank-limited route's 8192 rows (chi_E D^2 at
+    chi = 170, D = 8) and an unknown variant flag are rejected up front."""
+    for alt, half in ((False, False), (True, False), (False, True), (True, True)):
+        cfg = b.make_config(2, 2, 2, 8, 128, 128, "bf16x3", alt_yr=alt, half_teal=half)
+        assert b.workspace_size(cfg, True, 4, 4) > 0
+    with pytest.raises(b.CtmError):
+        b.workspace_size(b.make_config(1, 1, 2, 8, 170, 170, "bf16x3", half_teal=True))
+    assert b.workspace_size(b.make_config(1, 1, 4, 12, 170, 170, "bf16x3")) > 0
+    cfg = b.make_config(1, 1, 2, 2, 8, 8)
+    cfg.projector_variant = 4
+    with pytest.raises(b.CtmError):
+        b.workspace_size(cfg)
