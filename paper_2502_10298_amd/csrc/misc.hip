@@ -5,7 +5,6 @@
 #include "kernels.hpp"
 
 #include <cstdint>
-#include <type_traits>
 
 namespace sctm {
 
@@ -146,6 +145,27 @@ __global__ void transpose_kernel(const T* __restrict__ in, T* __restrict__ out, 
   }
 }
 
+// The permutation with the innermost output axis (innermost in the input
+// too) grouped into vectors V of VW elements; false (nothing launched) when
+// the run length, another input stride or the alignment does not allow it.
+template <typename V, int VW>
+static bool permute_vec(hipStream_t s, const void* in, void* out, const PermDesc& d, long n, bool acc) {
+  if (d.out_dims[d.rank - 1] % VW != 0 || ((uintptr_t)in | (uintptr_t)out) % sizeof(V) != 0) return false;
+  for (int i = 0; i + 1 < d.rank; ++i)
+    if (d.out_dims[i] > 1 && d.in_strides_perm[i] % VW != 0) return false;
+  PermGeneric gv;
+  gv.rank = d.rank;
+  for (int i = 0; i < d.rank; ++i) {
+    const bool inner = i == d.rank - 1;
+    gv.dv[i] = make_fastdiv((unsigned)(inner ? d.out_dims[i] / VW : d.out_dims[i]));
+    gv.istr[i] = inner ? 1u : (unsigned)(d.in_strides_perm[i] / VW);
+  }
+  const long nv = n / VW;
+  hipLaunchKernelGGL(permute32_kernel<V>, dim3(grid_for(nv)), dim3(256), 0, s, (const V*)in, (V*)out, gv,
+                     (unsigned)nv, acc);
+  return true;
+}
+
 template <typename T>
 static void launch_permute32(hipStream_t s, const void* in, void* out, const PermDesc& d, long n, bool acc) {
   // output strides (row-major over out_dims)
@@ -177,25 +197,12 @@ static void launch_permute32(hipStream_t s, const void* in, void* out, const Per
     return;
   }
   // innermost output axis also innermost in the input (contiguous runs of
-  // its length in both): the runs move as 16-byte vectors, every other
-  // input stride being a multiple of the run length
-  constexpr int VW = 16 / (int)sizeof(T);
-  bool vec_ok = yax == d.rank - 1 && d.out_dims[d.rank - 1] % VW == 0 && ((uintptr_t)in | (uintptr_t)out) % 16 == 0;
-  for (int i = 0; i + 1 < d.rank && vec_ok; ++i)
-    if (d.out_dims[i] > 1 && d.in_strides_perm[i] % VW != 0) vec_ok = false;
-  if (vec_ok) {
-    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
-    PermGeneric gv;
-    gv.rank = d.rank;
-    for (int i = 0; i < d.rank; ++i) {
-      const bool inner = i == d.rank - 1;
-      gv.dv[i] = make_fastdiv((unsigned)(inner ? d.out_dims[i] / VW : d.out_dims[i]));
-      gv.istr[i] = inner ? 1u : (unsigned)(d.in_strides_perm[i] / VW);
-    }
-    const long nv = n / VW;
-    hipLaunchKernelGGL(permute32_kernel<V>, dim3(grid_for(nv)), dim3(256), 0, s, (const V*)in, (V*)out, gv,
-                       (unsigned)nv, acc);
-    return;
+  // its length in both): the runs move as 16-byte (else 8-byte) vectors,
+  // every other input stride being a multiple of the vector width
+  if (yax == d.rank - 1 && d.rank > 1) {
+    if (sizeof(T) == 4 && permute_vec<float4, 4>(s, in, out, d, n, acc)) return;
+    if (sizeof(T) == 4 && permute_vec<float2, 2>(s, in, out, d, n, acc)) return;
+    if (sizeof(T) == 8 && permute_vec<double2, 2>(s, in, out, d, n, acc)) return;
   }
   PermGeneric gd;
   gd.rank = d.rank;
