@@ -559,3 +559,38 @@ def test_app_b_mixed_precision_energy(prec, tol, alt_yr, half_teal):
     env, A = _oracle_run_v(A_np, 8, 30, alt_yr, half_teal)
     e_ref, _ = sc.energy(env, A, 1, 1, h)
     assert abs(e_gpu - float(e_ref)) <= tol * abs(float(e_ref)), (e_gpu, float(e_ref))
+
+
+@pytest.fixture(scope="module")
+def converged_env_d2_chi8_alt():
+    """The oracle's environment of the d2_D2_chi8 workload after 20 sweeps
+    with the alternative yellow / red projectors of App. B."""
+    A_np = inp.workload_peps("d2_D2_chi8")
+    env, _ = _oracle_run_v(A_np, 8, 20, True, False)
+    return A_np, {k: {n: t.detach().numpy().copy() for n, t in e.items()} for k, e in env.items()}
+
+
+@pytest.mark.parametrize("prec,etol,gtol", [("fp64", 1e-10, 1e-8), ("fp32", 1e-6, 1e-5), ("bf16x6", 1e-6, 1e-5),
+                                            ("bf16x3", 5e-5, 5e-4)])
+def test_app_b_mixed_precision_gradient(prec, etol, gtol, converged_env_d2_chi8_alt):
+    """Energy and dE/dA through the alternative yellow / red projectors (2
+    sweeps from the oracle's converged start, D=2, chi=8) with reduced-
+    precision contractions against the FP64 oracle of the same construction,
+    to the bounds of the App. A test.  Measured (energy, gradient): FP64
+    2.1e-14, 2.9e-10; FP32 1.4e-8, 1.0e-6; BF16x6 3.0e-7, 4.8e-7; BF16x3
+    1.5e-5, 3.4e-5."""
+    A_np, env0 = converged_env_d2_chi8_alt
+    chi, ns = 8, 2
+    h = inp.heisenberg_h_rotated()
+    _say("app_b gradient d2 chi8 from a converged start", prec)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec=prec, with_grad=True, n_sweeps=ns, ckpt_every=1,
+                     alt_yr=True)
+    obj.env_import(torch.tensor(inp.pack_env(env0, 1, 1, 2, chi, chi), device=DEV))
+    e_gpu, dA = obj.energy_grad(h, ns, 1)
+    e_ref, g_ref = og.energy_and_grad(A_np, env0, chi, chi, ns, h, alt_yr=True)
+    g = dA.cpu().numpy()
+    eerr = abs(e_gpu - e_ref) / abs(e_ref)
+    gerr = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"[result] {prec}: energy rel err {eerr:.2e}, gradient rel err {gerr:.2e}", flush=True)
+    assert eerr <= etol, eerr
+    assert gerr <= gtol, gerr
