@@ -7,6 +7,11 @@ The gradient is reverse mode through every step including the projector SVDs
 (Sec. III: the gradient of the energy by reverse-mode AD through the CTMRG),
 using the broadened SVD rule of svd_adjoint.  Truncation ranks are fixed by
 the forward pass.
+
+Pinned by central finite differences at D = 2, chi = 4 (and D = 4, chi = 16,
+to 1e-8).  At D = 4, chi = 32 the gradient differs from smooth central
+differences by up to 6e-4 of its largest entry (an open deviation of the
+adjoint rule, recorded by an expected-failure test).
 """
 from __future__ import annotations
 

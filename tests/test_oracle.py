@@ -485,3 +485,28 @@ def test_interlayer_bond_below_environment_bond_converges():
         diffs.append(abs(float(es) - e_ref) / abs(e_ref))
     assert diffs[0] > diffs[1] > diffs[2]
     assert diffs[2] < 1e-5
+
+
+@pytest.mark.slow
+@pytest.mark.xfail(strict=False, reason="open: at D = 4, chi = 32 the broadened-SVD-adjoint gradient (oracle autograd; "
+                                        "the GPU adjoint follows it to 3e-7) differs from smooth central differences "
+                                        "by up to 6e-4 of its largest entry; at chi <= 16 it agrees to 1e-8")
+def test_gradient_matches_finite_differences_at_chi32():
+    """The finite-difference pin of the gradient at a larger bond dimension:
+    two sweeps from the oracle's converged D = 4, chi = 32 environment, the
+    largest entry and five seeded ones, to 1e-5 of the largest entry."""
+    name = "d2_D4_chi32"
+    A_np, h = inp.workload_peps(name), inp.workload_h(name)
+    chi, ns = 32, 2
+    A = sc.peps_from_numpy(A_np)
+    env, _, _ = sc.run(sc.init_identity(1, 1, 4), A, 1, 1, chi, chi, 20)
+    env0 = {k: {n: t.detach().numpy().copy() for n, t in e.items()} for k, e in env.items()}
+    _, g = og.energy_and_grad(A_np, env0, chi, chi, ns, h)
+    gf = g.reshape(-1)
+    gmax = float(np.abs(gf).max())
+    rng = np.random.default_rng(3)
+    for i in [int(np.argmax(np.abs(gf)))] + list(rng.choice(gf.size, 5, replace=False)):
+        d = np.zeros(gf.size)
+        d[i] = 1.0
+        fd = og.central_difference4(A_np, env0, chi, chi, ns, h, d.reshape(A_np.shape), step=1e-4)
+        assert abs(fd - gf[i]) <= 1e-5 * gmax, (i, fd, gf[i])
