@@ -10,10 +10,15 @@ Sec. III; Liao et al. 2019 and Townsend 2016 for the formula):
                + S (F o (V^T Vbar - Vbar^T V)) ] V^T
 
 with F_ij = 1 / (s_j^2 - s_i^2), here broadened to
-F_ij = (s_j^2 - s_i^2) / ((s_j^2 - s_i^2)^2 + eps_F), eps_F = (eps_rel s_1^2)^2,
-and F_ii = 0: the Lorentzian only acts where |s_j^2 - s_i^2| < eps_rel s_1^2
-(the broadening scale has the units of s^2, so eps_F has those of s^4).  For a square matrix with full U and V there is no
-complement-space term; zero singular values are handled by the same formula.
+F_ij = (s_j^2 - s_i^2) / ((s_j^2 - s_i^2)^2 + eps_ij),
+eps_ij = (eps_rel (s_i^2 + s_j^2))^2, and F_ii = 0: the Lorentzian only acts
+on pairs whose gap is below eps_rel of their own scale (near-degenerate
+pairs), so that pairs of small but well-separated singular values, and a
+small one against the zero ones of a rank-deficient M, keep the exact F.  (A
+single scale eps_rel s_1^2 would damp every pair below sqrt(eps_rel) s_1,
+which a graded spectrum reaches: the gradient then misses the derivative.)
+For a square matrix with full U and V there is no complement-space term;
+zero singular values are handled by the same formula.
 """
 from __future__ import annotations
 
@@ -35,8 +40,9 @@ class BroadenedSVD(torch.autograd.Function):
         n = S.shape[0]
         s2 = S * S
         d = s2[None, :] - s2[:, None]                     # d_ij = s_j^2 - s_i^2
-        eps = (ctx.eps_rel * s2[0]) ** 2 if n else 0.0
-        F = d / (d * d + eps) if eps > 0 else torch.where(d != 0, 1.0 / d, torch.zeros_like(d))
+        eps = (ctx.eps_rel * (s2[None, :] + s2[:, None])) ** 2
+        den = d * d + eps
+        F = torch.where(den > 0, d / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(d))
         F.fill_diagonal_(0.0)
         inner = torch.zeros((n, n), dtype=U.dtype)
         if gU is not None:

@@ -98,13 +98,17 @@ hipError_t zero_rows_from(hipStream_t s, int nb, int chi, double* GU, double* GV
   return hipGetLastError();
 }
 
+// F_ij = d / (d^2 + (eps (s_i^2 + s_j^2))^2), d = s_j^2 - s_i^2: the
+// Lorentzian acts only on pairs whose gap is below eps of their own scale,
+// so small but well-separated singular values keep the exact 1 / d
 __device__ inline double inner_val(int i, int j, int nb, int chi, int r, const double* S, const double* Sb,
-                                   const double* GU, const double* GV, double eps2) {
+                                   const double* GU, const double* GV, double eps) {
   if (i >= r || j >= r) return 0.0;
   if (i == j) return (i < chi) ? Sb[i] : 0.0;
   double si = S[i], sj = S[j];
   double d = sj * sj - si * si;
-  double F = d / (d * d + eps2);
+  double e = eps * (si * si + sj * sj);
+  double F = d / (d * d + e * e);
   double gu = (j < chi ? GU[(long)i * chi + j] : 0.0) - (i < chi ? GU[(long)j * chi + i] : 0.0);
   double gv = (j < chi ? GV[(long)i * chi + j] : 0.0) - (i < chi ? GV[(long)j * chi + i] : 0.0);
   return F * (gu * sj + si * gv);
@@ -113,18 +117,15 @@ __device__ inline double inner_val(int i, int j, int nb, int chi, int r, const d
 __global__ void svd_adj_inner_kernel(int nb, int c2, int chi, const double* S, const double* Sb, const double* GU,
                                      const double* GV, const int* kr, double eps, double* Itop, double* Ileft) {
   const int r = kr[1];
-  const double s1 = S[0];
-  const double e = eps * s1 * s1;
-  const double eps2 = e * e;
   long ntop = (long)c2 * nb, nleft = (long)(nb - c2) * c2;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < ntop + nleft; t += (long)gridDim.x * blockDim.x) {
     if (t < ntop) {
       int i = (int)(t / nb), j = (int)(t % nb);
-      Itop[t] = inner_val(i, j, nb, chi, r, S, Sb, GU, GV, eps2);
+      Itop[t] = inner_val(i, j, nb, chi, r, S, Sb, GU, GV, eps);
     } else {
       long u = t - ntop;
       int i = c2 + (int)(u / c2), j = (int)(u % c2);
-      Ileft[u] = inner_val(i, j, nb, chi, r, S, Sb, GU, GV, eps2);
+      Ileft[u] = inner_val(i, j, nb, chi, r, S, Sb, GU, GV, eps);
     }
   }
 }

@@ -995,7 +995,7 @@ void Engine::backward() {
 //   Ubar_k = Xbar S^{-1/2}, Vbar_k = Ybar S^{-1/2},
 //   Sbar_k = -1/2 S^{-3/2} diag(U_k^T Xbar + V_k^T Ybar),
 //   Mbar by the thin-SVD adjoint over the r = #{s > 1e-14 s_1} leading
-//   triplets with the Lorentzian-broadened F (eps_F = (adj_eps s_1^2)^2):
+//   triplets with the Lorentzian-broadened F (eps_ij = (adj_eps (s_i^2 + s_j^2))^2):
 //   Mbar = U [F o (G_U - G_U^T) S + S F o (G_V - G_V^T) + diag(Sbar)] V^T
 //          + (Ubar - U G_U) S^{-1} V^T + U S^{-1} (Vbar - V G_V)^T,
 //   G_U = U_r^T Ubar, G_V = V_r^T Vbar; then rho_Bbar += rho_T Mbar^T,

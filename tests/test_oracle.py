@@ -488,13 +488,13 @@ def test_interlayer_bond_below_environment_bond_converges():
 
 
 @pytest.mark.slow
-@pytest.mark.xfail(strict=False, reason="open: at D = 4, chi = 32 the broadened-SVD-adjoint gradient (oracle autograd; "
-                                        "the GPU adjoint follows it to 3e-7) differs from smooth central differences "
-                                        "by up to 6e-4 of its largest entry; at chi <= 16 it agrees to 1e-8")
 def test_gradient_matches_finite_differences_at_chi32():
     """The finite-difference pin of the gradient at a larger bond dimension:
     two sweeps from the oracle's converged D = 4, chi = 32 environment, the
-    largest entry and five seeded ones, to 1e-5 of the largest entry."""
+    largest entry and five seeded ones, to 1e-5 of the largest entry.  The
+    kept spectra here reach far below 1e-6 s_1, where a broadening on the
+    single scale s_1^2 damped the exact F and missed the derivative by up to
+    6e-4 of the largest entry."""
     name = "d2_D4_chi32"
     A_np, h = inp.workload_peps(name), inp.workload_h(name)
     chi, ns = 32, 2
