@@ -9,7 +9,9 @@ split_ctmrg
     The split-CTMRG method (torch CPU float64): projector recipe, one left
     move with green/yellow then teal/red projectors, the other three moves by
     lattice symmetry, sweeps, the nearest-neighbour energy, Ising free energy
-    and magnetisation helpers.
+    and magnetisation helpers; the App. B constructions (alternative
+    yellow / red projectors with the physical leg cut by yellow, teal half
+    projectors) behind the alt_yr / half_teal flags.
 svd_adjoint
     Broadened SVD used by the oracle gradient (torch autograd Function).
 grad
@@ -24,5 +26,8 @@ Parity status: the teal and red half networks are a reading of the paper
 (Ising closed forms, product states, agreement with the conventional CTMRG,
 2x2 cell = 1x1 cell for a translation-invariant state), not network by
 network: "parity unpinned" at the level of the individual teal / red
-networks.
+networks.  The same holds for the teal half networks of App. B (their figure
+has no body either): pinned end to end by product states, Onsager and
+convergence to the conventional CTMRG.  The alternative yellow / red networks
+follow complete figures and are pinned the same way, plus exact half-steps.
 """
