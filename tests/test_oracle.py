@@ -329,6 +329,76 @@ def test_ising_spontaneous_magnetisation(beta, tol):
 
 
 # ---------------------------------------------------------------------------
+# the convergence measure (Sec. II B: the iteration runs to a fixed point of
+# the environment, read here as one of the corners' singular values)
+# ---------------------------------------------------------------------------
+def _orth(n, seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, n)))
+    return q
+
+
+def _corner(s, seed):
+    """A corner with singular values s in a random orthogonal gauge."""
+    n = len(s)
+    return torch.tensor(_orth(n, seed) @ np.diag(s) @ _orth(n, seed + 1).T, dtype=DT)
+
+
+def test_convergence_measure_hand_computed():
+    """Delta is the largest, over the corners, of the 2-norm of the change of
+    the singular values, the shorter spectrum padded with zeros.  Corners in
+    random orthogonal gauges with known spectra:
+      C1: (3, 2, 1) -> (3, 2)            change (0, 0, -1): norm 1
+      C2: (1, 0.5) -> (0.8, 0.5, 0.1)    change (-0.2, 0, 0.1): norm sqrt(0.05)
+      C3: (2, 1) -> (2.5, 1)             change (0.5, 0): norm 0.5
+      C4: equal spectra, other gauge     change 0
+    so Delta = 1; with C1 unchanged it is 0.5; and the measure does not see
+    the gauge."""
+    old = {"C1": (3, 2, 1), "C2": (1, 0.5), "C3": (2, 1), "C4": (4, 3, 2, 1)}
+    new = {"C1": (3, 2), "C2": (0.8, 0.5, 0.1), "C3": (2.5, 1), "C4": (4, 3, 2, 1)}
+    e_old = {(0, 0): {c: _corner(np.array(v, float), 10 + i) for i, (c, v) in enumerate(old.items())}}
+    e_new = {(0, 0): {c: _corner(np.array(v, float), 30 + i) for i, (c, v) in enumerate(new.items())}}
+    s_old, s_new = sc.corner_spectra(e_old), sc.corner_spectra(e_new)
+    assert abs(sc.spectra_delta(s_old, s_new) - 1.0) < 1e-13
+    assert abs(sc.spectra_delta(s_new, s_old) - 1.0) < 1e-13
+    e_new[(0, 0)]["C1"] = _corner(np.array(old["C1"], float), 50)
+    assert abs(sc.spectra_delta(s_old, sc.corner_spectra(e_new)) - 0.5) < 1e-13
+    e_new[(0, 0)]["C3"] = _corner(np.array(old["C3"], float), 52)
+    assert abs(sc.spectra_delta(s_old, sc.corner_spectra(e_new)) - math.sqrt(0.05)) < 1e-13
+    e_new[(0, 0)]["C2"] = _corner(np.array(old["C2"], float), 54)
+    assert sc.spectra_delta(s_old, sc.corner_spectra(e_new)) < 1e-14
+
+
+def test_convergence_measure_of_run():
+    """run() compares every sweep with the spectra of its start environment:
+    one sweep from the identity boundary (every corner [[1]]) gives the
+    change of the new corners' zero-padded spectra against (1, 0, ...);
+    at a converged environment (Ising PEPS in its disordered phase, where
+    the fixed point is approached geometrically) a further sweep changes the
+    spectra by less than 1e-10 (the rounding-level rotations of the
+    truncated corner spectrum stop it from going much lower at chi = 8), and
+    run() stops at the first sweep whose
+    change is below tol."""
+    A = sc.peps_from_numpy(inp.peps_ising(0.3))
+    env0 = sc.init_identity(1, 1, 2)
+    env1, n1, d1 = sc.run(env0, A, 1, 1, 8, 8, 1)
+    hand = 0.0
+    for c in ("C1", "C2", "C3", "C4"):
+        s = np.linalg.svd(env1[(0, 0)][c].detach().numpy(), compute_uv=False)
+        ref = np.zeros(len(s))
+        ref[0] = 1.0
+        hand = max(hand, float(np.linalg.norm(s - ref)))
+    assert n1 == 1 and 1e-3 < d1 and abs(d1 - hand) < 1e-13
+    env, n, d = sc.run(env0, A, 1, 1, 8, 8, 80, tol=1e-10)
+    assert d < 1e-10 and n < 80
+    _, n2, d2 = sc.run(env, A, 1, 1, 8, 8, 1)
+    assert n2 == 1 and d2 < 1e-10
+    # stopping: the sweep count is the first whose change is below tol
+    _, n3, d3 = sc.run(env0, A, 1, 1, 8, 8, 80, tol=1e-6)
+    _, _, d_before = sc.run(env0, A, 1, 1, 8, 8, n3 - 1, tol=0.0) if n3 > 1 else (None, 0, math.inf)
+    assert d3 < 1e-6 <= d_before
+
+
+# ---------------------------------------------------------------------------
 # split environment vs the independent conventional CTMRG
 # ---------------------------------------------------------------------------
 def _merge(e):
