@@ -100,18 +100,37 @@ typedef struct ctm_ctx ctm_ctx;
  * with_grad != 0 reserves what ctm_energy_grad(n_sweeps, ckpt_every) needs. */
 ctm_status ctm_workspace_size(const ctm_config* cfg, int with_grad, int n_sweeps, int ckpt_every, size_t* bytes);
 
-/* Create a context: copies A (device, FP64, layout above) into the workspace,
- * writes the initial environment (boundary_vec_host: length D, PRODUCT only,
- * else NULL) and keeps it as the start environment of ctm_energy_grad. */
+/* Create a context for the unit cell {A[x][y]} of Sec. II A (the
+ * coefficient tensor network of the iPEPS, one real tensor per site of the
+ * periodic cell) and the split environment of Sec. II B with bond dimensions
+ * chi_E (environment) and chi_I (interlayer).  Copies A (device, FP64, layout
+ * above; the caller keeps ownership) into the workspace, writes the initial
+ * environment (boundary_vec_host: length D, PRODUCT only, else NULL) and
+ * keeps it as the start environment of ctm_energy_grad.  The workspace
+ * (device, ws_bytes >= ctm_workspace_size) belongs to the caller and must
+ * outlive the context.  CTM_EINVAL for an invalid configuration, a NULL A or
+ * workspace, or a workspace too small for the persistent part; *out is then
+ * NULL. */
 ctm_status ctm_init(const ctm_config* cfg, const double* A_dev, const double* boundary_vec_host, void* workspace_dev,
                     size_t ws_bytes, void* hip_stream, ctm_ctx** out);
 
-/* Directional sweeps (left, top, right, bottom move; Sec. II B) until the
- * corner singular values change by less than tol (2-norm, largest over all
- * corners) or max_sweeps are done.  tol <= 0 runs exactly max_sweeps. */
+/* Directional sweeps (left, top, right, bottom move; Sec. II B, Eqs.
+ * splitCTMRG_C1, splitCTMRG_C4, splitCTMRG_Tket, splitCTMRG_Tbra for the left
+ * move, the others by lattice symmetry) until the corner singular values
+ * change by less than tol over one sweep (2-norm of the difference of the
+ * zero-padded spectra, largest over all corners of the cell) or max_sweeps
+ * are done.  tol <= 0 runs exactly max_sweeps.  *delta (optional) = that
+ * change over the last sweep run (the spectra of the sweep's start
+ * environment are taken first when they are not known).  CTM_ENOTCONV when
+ * tol > 0 was not reached (the environment is valid); CTM_ENUMERIC for a
+ * non-finite change. */
 ctm_status ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done, double* delta);
 
-/* The four projector pairs of the move in `direction` (0 left, 1 top,
+/* Projectors of Fig. proj_plots_green (the recipe: the product of the two
+ * half networks over the legs to keep, its truncated SVD, and the pair
+ * P_T = rho_B U_k S_k^{-1/2}, P_B = rho_T V_k S_k^{-1/2}) for the four
+ * colours of App. A.
+ * The four projector pairs of the move in `direction` (0 left, 1 top,
  * 2 right, 3 bottom) for the cut below row x / row x of the column holding
  * site [x][y] (in that move's frame), from the current environment, which is
  * not modified.  out_dev (FP64, device) receives, in order, green P_T, P_B
@@ -123,7 +142,23 @@ ctm_status ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done,
 ctm_status ctm_projectors(ctm_ctx* ctx, int direction, int x, int y, double* out_dev, double* trunc_err_host);
 size_t ctm_projectors_elems(const ctm_config* cfg);
 
-/* Energy per site of the nearest-neighbour Hamiltonian h (host, FP64,
+/* One column of one directional move (Sec. II B: the left move absorbs the
+ * columns of the cell one after the other, Eqs. splitCTMRG_C1,
+ * splitCTMRG_C4, splitCTMRG_Tket, splitCTMRG_Tbra): in the frame of
+ * `direction` (0 left, 1 top, 2 right, 3 bottom, as in ctm_projectors),
+ * column y of the cell is absorbed into the left environment of column y+1,
+ * whose C1, T4k, T4b, C4 (in that frame) are replaced in the current
+ * environment; nothing else changes.  A sweep is the four moves, each over
+ * every column in order.  For checks of a single step at full size.
+ * CTM_EINVAL for a direction outside 0..3 or a column outside the frame's
+ * cell. */
+ctm_status ctm_move_column(ctm_ctx* ctx, int direction, int y);
+
+/* Sec. III: the expectation value of a nearest-neighbour Hamiltonian from
+ * the converged environment, each bond's two-site reduced density matrix
+ * being the 2-row patch of Fig. proj_plots_green with both physical legs
+ * open.  The final reduction is FP64 on the GPU.
+ * Energy per site of the nearest-neighbour Hamiltonian h (host, FP64,
  * p^2 x p^2 row-major, rows (s1 s2) bra, columns (s1 s2) ket, s1 = upper or
  * left site).  e_bonds (host, optional) = [Lx][Ly][2] horizontal, vertical
  * bond energies of each site. */
@@ -137,11 +172,17 @@ ctm_status ctm_energy(ctm_ctx* ctx, const double* h_host, double* e_site, double
  * out over the four bonds of a site. */
 ctm_status ctm_energy_hv(ctm_ctx* ctx, const double* h_host, const double* hv_host, double* e_site, double* e_bonds);
 
-/* E(A) = energy after exactly n_sweeps sweeps from the start environment, and
- * dE/dA (device, FP64, layout of A) by reverse mode with the hand-written
- * adjoints; the environment is checkpointed every ckpt_every sweeps and the
- * sweeps of each block are recomputed in the backward pass.  The current
- * environment is left at the state after the n_sweeps sweeps. */
+/* Sec. III (the gradient of the variational energy by reverse-mode
+ * differentiation through the CTMRG, at the cost of the CTMRG itself):
+ * E(A) = energy after exactly n_sweeps sweeps from the start environment, and
+ * dE/dA (device, FP64, layout of A, written by the call; the caller owns it)
+ * by reverse mode with the hand-written adjoints; the environment is
+ * checkpointed every ckpt_every sweeps and the sweeps of each block are
+ * recomputed in the backward pass.  The current environment is left at the
+ * state after the n_sweeps sweeps (also when n_sweeps is not a multiple of
+ * ckpt_every).  CTM_EINVAL for n_sweeps < 0, ckpt_every < 1, NULL pointers
+ * or a workspace sized for fewer sweeps per block; CTM_ENUMERIC for a
+ * non-finite energy. */
 ctm_status ctm_energy_grad(ctm_ctx* ctx, const double* h_host, int n_sweeps, int ckpt_every, double* e_site,
                            double* dA_dev);
 /* As ctm_energy_grad with separate horizontal (h_host) and vertical

@@ -12,6 +12,7 @@ import os
 from dataclasses import dataclass
 
 import numpy as np
+import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsplitctm.so")
@@ -21,6 +22,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 INIT = {"identity": 0, "product": 1}
 
 EXPORTED = ("ctm_workspace_size", "ctm_init", "ctm_sweep", "ctm_projectors", "ctm_projectors_elems",
+            "ctm_move_column",
             "ctm_energy", "ctm_energy_grad", "ctm_env_elems", "ctm_env_export", "ctm_env_import",
             "ctm_energy_hv", "ctm_energy_grad_hv", "ctm_last_stats", "ctm_debug_gemm_work_bytes", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd", "ctm_debug_qr_work_bytes", "ctm_debug_qr",
             "ctm_kernel_timing_enable", "ctm_kernel_timing", "ctm_destroy", "ctm_strerror")
@@ -60,6 +62,7 @@ def lib() -> ctypes.CDLL:
         "ctm_sweep": (I, [P, I, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
         "ctm_projectors": (I, [P, I, I, I, P, P]),
         "ctm_projectors_elems": (S, [cfgp]),
+        "ctm_move_column": (I, [P, I, I]),
         "ctm_energy": (I, [P, P, ctypes.POINTER(D), P]),
         "ctm_energy_grad": (I, [P, P, I, I, ctypes.POINTER(D), P]),
         "ctm_energy_hv": (I, [P, P, P, ctypes.POINTER(D), P]),
@@ -126,7 +129,6 @@ class SplitCTM:
     def __init__(self, A, chi_E, chi_I=None, prec="fp64", init="identity", boundary=None,
                  with_grad=False, n_sweeps=0, ckpt_every=1, cutoff=1e-12, adj_eps=1e-12,
                  workspace_bytes=None, stream=None, alt_yr=False, half_teal=False):
-        import torch
         self.torch = torch
         if A.dtype != torch.float64 or not A.is_cuda or A.dim() != 7:
             raise ValueError("A must be a CUDA float64 tensor [Lx, Ly, p, D, D, D, D]")
@@ -168,6 +170,12 @@ class SplitCTM:
         if check and st not in (CTM_OK, CTM_ENOTCONV):
             raise CtmError(st, "ctm_sweep")
         return st, n.value, d.value
+
+    def move_column(self, direction, y):
+        """One column of one directional move (ctm_move_column)."""
+        st = lib().ctm_move_column(self.h, direction, y)
+        if st != CTM_OK:
+            raise CtmError(st, "ctm_move_column")
 
     def energy(self, h, h_v=None):
         """Energy per site; h on horizontal bonds, h_v (default h) on vertical ones."""
@@ -259,7 +267,6 @@ class SplitCTM:
 
 
 def debug_gemm(A, B, transA=False, transB=False, prec="fp64", stream=None, split_k=True):
-    import torch
     M = A.shape[1] if transA else A.shape[0]
     K = A.shape[0] if transA else A.shape[1]
     N = B.shape[0] if transB else B.shape[1]
@@ -275,7 +282,6 @@ def debug_gemm(A, B, transA=False, transB=False, prec="fp64", stream=None, split
 
 
 def debug_svd(M, stream=None, max_sweeps=0):
-    import torch
     if M.dim() == 2:
         M = M[None]
     b, n, _ = M.shape
@@ -295,7 +301,6 @@ def debug_svd(M, stream=None, max_sweeps=0):
 def debug_qr(X, stream=None):
     """Thin QR of a batch of tall matrices X [batch, m, k] (FP64, device):
     returns (Q [batch, m, k], R [batch, k, k])."""
-    import torch
     if X.dim() == 2:
         X = X[None]
     b, m, k = X.shape
@@ -309,27 +314,45 @@ def debug_qr(X, stream=None):
     return Qt.transpose(1, 2), R
 
 
-class CtmEnergy:
-    """E(A) with dE/dA from the library's hand-written adjoints, usable as a
-    torch.autograd.Function: CtmEnergy.apply(A, h, chi, n_sweeps, ...)."""
+class CtmEnergy(torch.autograd.Function):
+    """E(A) after a fixed number of split-CTMRG sweeps, with dE/dA from the
+    library's hand-written adjoints (Sec. III: the gradient by reverse mode
+    through the CTMRG).  Call it through `ctm_energy` (keyword arguments);
+    the positional form is
+
+        CtmEnergy.apply(A, h, chi_E, n_sweeps, ckpt_every, prec, chi_I, h_v,
+                        alt_yr, half_teal, cutoff, state)
+
+    A: FP64 device tensor [Lx, Ly, p, D, D, D, D]; h (h_v): FP64 host arrays
+    p^2 x p^2, the horizontal (vertical) bond Hamiltonian; state: None, or a
+    dict whose "env" entry (packed FP64 device environment) is the start
+    environment of the sweeps and receives the environment after them, so
+    that successive calls (an optimiser's steps) start from the last one.
+    Each call builds its own context: the library copies A at init."""
 
     @staticmethod
-    def make(torch):
-        class _F(torch.autograd.Function):
-            @staticmethod
-            def forward(ctx, A, h, chi, n_sweeps, ckpt_every, prec, env0):
-                obj = SplitCTM(A.detach(), chi, chi, prec=prec, with_grad=True, n_sweeps=n_sweeps,
-                               ckpt_every=ckpt_every)
-                if env0 is not None:
-                    obj.env_import(env0)
-                e, dA = obj.energy_grad(h, n_sweeps, ckpt_every)
-                obj.close()
-                ctx.save_for_backward(dA)
-                return torch.tensor(e, dtype=torch.float64, device=A.device)
+    def forward(ctx, A, h, chi_E, n_sweeps, ckpt_every, prec, chi_I, h_v, alt_yr, half_teal, cutoff, state):
+        obj = SplitCTM(A.detach(), chi_E, chi_I if chi_I is not None else chi_E, prec=prec, with_grad=True,
+                       n_sweeps=n_sweeps, ckpt_every=ckpt_every, cutoff=cutoff, alt_yr=alt_yr,
+                       half_teal=half_teal)
+        try:
+            if state is not None and state.get("env") is not None:
+                obj.env_import(state["env"])
+            e, dA = obj.energy_grad(h, n_sweeps, ckpt_every, h_v=h_v)
+            if state is not None:
+                state["env"] = obj.env_export()
+        finally:
+            obj.close()
+        ctx.save_for_backward(dA)
+        return torch.tensor(e, dtype=torch.float64, device=A.device)
 
-            @staticmethod
-            def backward(ctx, ge):
-                (dA,) = ctx.saved_tensors
-                return ge * dA, None, None, None, None, None, None
+    @staticmethod
+    def backward(ctx, ge):
+        (dA,) = ctx.saved_tensors
+        return (ge * dA,) + (None,) * 11
 
-        return _F
+
+def ctm_energy(A, h, chi_E, n_sweeps, ckpt_every=1, prec="fp64", chi_I=None, h_v=None, alt_yr=False,
+               half_teal=False, cutoff=1e-12, state=None):
+    """Differentiable energy per site E(A) (see CtmEnergy)."""
+    return CtmEnergy.apply(A, h, chi_E, n_sweeps, ckpt_every, prec, chi_I, h_v, alt_yr, half_teal, cutoff, state)

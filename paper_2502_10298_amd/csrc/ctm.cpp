@@ -53,7 +53,7 @@ struct ctm_ctx {
   Ten h64v;                // FP64 [p^2][p^2], vertical bonds
   size_t transient_mark = 0;
   int host_flags[256];
-  bool have_spec = false;
+  bool spec_current = false;   // spec_prev holds the spectra of the current environment
   double last_flops = 0, last_sweeps = 0;
   bool timing = false;     // HIP-event timing of the GEMM and Jacobi launches
   KernelTimer timer;
@@ -707,7 +707,11 @@ void init_persistent(ctm_ctx* c, const double* A_dev, const double* bvec) {
   c->transient_mark = E.ar.mark();
 }
 
-// Corner spectra -> delta (largest 2-norm change), updates spec_prev.
+// Corner spectra of the current environment -> spec_prev.  Returns the
+// largest 2-norm change of any corner's spectrum against the spectra held
+// before (Sec. II B: the iteration stops at a fixed point of the corners), or
+// INFINITY when those were not the spectra of the environment this one was
+// computed from.
 double corner_delta(ctm_ctx* c) {
   Engine& E = c->E;
   const int nc = c->Lx * c->Ly * 4, ch = c->chiE;
@@ -733,11 +737,11 @@ double corner_delta(ctm_ctx* c) {
     int sw = 0;
     E.check(svd_f64(E.s, ch, nc, Cs.f64(), U.f64(), S.f64(), V.f64(), work, E.svd_max_sweeps, E.svd_tol,
                     c->host_flags, &sw));
-    E.check(spectra_delta(E.s, nc, ch, S.f64(), c->spec_prev.f64(), d.f64(), c->have_spec ? 1 : 0));
+    E.check(spectra_delta(E.s, nc, ch, S.f64(), c->spec_prev.f64(), d.f64(), c->spec_current ? 1 : 0));
     E.check(hipMemcpyAsync(&delta, d.p, sizeof(double), hipMemcpyDeviceToHost, E.s));
     E.check(hipStreamSynchronize(E.s));
-    if (!c->have_spec) delta = INFINITY;
-    c->have_spec = true;
+    if (!c->spec_current) delta = INFINITY;
+    c->spec_current = true;
   }
   E.ar.release(mk);
   return delta;
@@ -800,12 +804,16 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_h
       E.ar.release(mk);
     }
     E.svdc_select(-1, 0);
-    if ((s + 1) % ckpt == 0 && (s + 1) / ckpt <= nblk && !E.dry && E.ok())
+    if ((s + 1) % ckpt == 0 && (s + 1) / ckpt < nblk && !E.dry && E.ok())
       E.check(hipMemcpyAsync(ck[(s + 1) / ckpt].p, c->cur_blk.p, c->cur_blk.bytes(), hipMemcpyDeviceToDevice, E.s));
     if (E.dry) break;   // the workspace peak repeats every sweep
   }
   if (n_sweeps == 0 && !E.dry && E.ok())
     E.check(hipMemcpyAsync(c->cur_blk.p, ck[0].p, ck[0].bytes(), hipMemcpyDeviceToDevice, E.s));
+  // the state after the n_sweeps sweeps (the last block may be shorter than
+  // ckpt sweeps), restored into the current environment at the end
+  if (nblk > 0 && !E.dry && E.ok())
+    E.check(hipMemcpyAsync(ck[nblk].p, c->cur_blk.p, c->cur_blk.bytes(), hipMemcpyDeviceToDevice, E.s));
   // ---- energy (taped) and its reverse pass -> cotangent of the final env ----
   double esum = 0.0;
   {
@@ -1044,6 +1052,9 @@ ctm_status ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, d
   double d = INFINITY;
   bool conv = false;
   for (int s = 0; s < max_sweeps && E.ok(); ++s) {
+    // a measured sweep compares with the spectra of its own start environment
+    const bool measure = tol > 0 || (delta && s == max_sweeps - 1);
+    if (measure && !c->spec_current) corner_delta(c);
     for (int dir = 0; dir < 4 && E.ok(); ++dir) {
       size_t mk = E.ar.mark();
       Env env = view_env(*c, c->cur_blk);
@@ -1052,7 +1063,8 @@ ctm_status ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, d
       E.ar.release(mk);
     }
     ++done;
-    if (tol > 0 || (delta && s == max_sweeps - 1)) {
+    c->spec_current = false;
+    if (measure) {
       d = corner_delta(c);
       if (!(d == d)) {
         if (sweeps_done) *sweeps_done = done;
@@ -1164,6 +1176,31 @@ ctm_status ctm_projectors(ctm_ctx* c, int direction, int x, int y, double* out_d
   return finish(c, (ctm_status)status_from_engine(E));
 }
 
+ctm_status ctm_move_column(ctm_ctx* c, int direction, int y) {
+  if (!c || direction < 0 || direction > 3) return CTM_EINVAL;
+  const int ny = (direction == 1 || direction == 3) ? c->Lx : c->Ly;   // columns in the move's frame
+  if (y < 0 || y >= ny) return CTM_EINVAL;
+  Engine& E = c->E;
+  begin(c);
+  const Peps A = peps_view(*c, c->Aflat);
+  {
+    size_t mk = E.ar.mark();
+    Env env = view_env(*c, c->cur_blk);
+    Env fe;
+    Peps fa;
+    to_frame(E, direction, env, A, fe, fa);
+    // frame column y holds the sites that direction's move absorbs y-th
+    left_column(*c, fe, fa, y, nullptr, -1, direction);
+    Env out;
+    from_frame(E, direction, fe, out);
+    store_env(*c, out, c->cur_blk);
+    E.ar.release(mk);
+  }
+  c->spec_current = false;
+  if (E.ok()) E.check(hipStreamSynchronize(E.s));
+  return finish(c, (ctm_status)status_from_engine(E));
+}
+
 ctm_status ctm_energy_grad(ctm_ctx* c, const double* h_host, int n_sweeps, int ckpt_every, double* e_site,
                            double* dA_dev) {
   return ctm_energy_grad_hv(c, h_host, h_host, n_sweeps, ckpt_every, e_site, dA_dev);
@@ -1173,7 +1210,7 @@ ctm_status ctm_energy_grad_hv(ctm_ctx* c, const double* h_host, const double* hv
                               double* e_site, double* dA_dev) {
   if (!c || !h_host || !hv_host || !dA_dev || n_sweeps < 0 || ckpt_every < 1) return CTM_EINVAL;
   begin(c);
-  c->have_spec = false;
+  c->spec_current = false;
   ctm_status st = energy_grad_impl(c, h_host, hv_host, n_sweeps, ckpt_every, e_site, dA_dev);
   return finish(c, st);
 }
@@ -1198,7 +1235,7 @@ ctm_status ctm_env_import(ctm_ctx* c, const double* env_dev) {
     E.check(cast_f64_to_f32(E.s, env_dev, c->cur_blk.f32(), c->cur_blk.n()));
   E.check(hipMemcpyAsync(c->start_blk.p, c->cur_blk.p, c->cur_blk.bytes(), hipMemcpyDeviceToDevice, E.s));
   E.check(hipStreamSynchronize(E.s));
-  c->have_spec = false;
+  c->spec_current = false;
   return (ctm_status)status_from_engine(E);
 }
 

@@ -246,6 +246,87 @@ def test_gradient_checkpoint_blocks_agree():
         assert torch.allclose(g, out[0][1], atol=1e-11 * float(out[0][1].abs().max()))
 
 
+@pytest.mark.parametrize("ns,k", [(3, 2), (7, 5), (4, 4)])
+def test_energy_grad_leaves_environment_after_n_sweeps(ns, k):
+    """After ctm_energy_grad(n, k) the context holds the environment after the
+    n sweeps, also when n is not a multiple of k (the last checkpoint block
+    is then shorter): it equals the environment of n plain sweeps from the
+    same start, and a following energy equals the energy of that state."""
+    A_np = inp.peps_gaussian(12, 1, 1, 2, 2)
+    chi = 4
+    env0 = torch.tensor(inp.pack_env(inp.random_env(6, 1, 1, 2, chi, chi), 1, 1, 2, chi, chi), device=DEV)
+    h = inp.heisenberg_h_rotated()
+    _say(f"state after energy_grad({ns}, {k})")
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec="fp64", with_grad=True, n_sweeps=ns, ckpt_every=k)
+    obj.env_import(env0)
+    e_grad, _ = obj.energy_grad(h, ns, k)
+    after_grad = obj.env_export()
+    e_after, _ = obj.energy(h)
+    obj.env_import(env0)
+    obj.sweep(ns)
+    after_sweeps = obj.env_export()
+    obj.close()
+    scale = float(after_sweeps.abs().max())
+    assert torch.allclose(after_grad, after_sweeps, atol=1e-13 * scale, rtol=0)
+    assert abs(e_after - e_grad) <= 1e-13
+
+
+def test_ctm_energy_autograd_function():
+    """torch.autograd through CtmEnergy: dE/dA equals the library's
+    energy_grad and the oracle's autograd gradient (D = 2, chi = 4, 2 sweeps
+    from a random start, to 1e-8), and follows the upstream cotangent (the
+    gradient of 3 E is 3 dE/dA)."""
+    A_np = inp.peps_gaussian(11, 1, 1, 2, 2)
+    chi, ns = 4, 2
+    env0_np = inp.random_env(5, 1, 1, 2, chi, chi)
+    env0 = torch.tensor(inp.pack_env(env0_np, 1, 1, 2, chi, chi), device=DEV)
+    h = inp.heisenberg_h_rotated()
+    _say("CtmEnergy autograd d2 chi4 fp64")
+    A = torch.tensor(A_np, device=DEV, requires_grad=True)
+    e = b.ctm_energy(A, h, chi, ns, ckpt_every=1, state={"env": env0})
+    (g,) = torch.autograd.grad(e, A)
+    A2 = torch.tensor(A_np, device=DEV, requires_grad=True)
+    (g3,) = torch.autograd.grad(3.0 * b.ctm_energy(A2, h, chi, ns, ckpt_every=1, state={"env": env0}), A2)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, prec="fp64", with_grad=True, n_sweeps=ns, ckpt_every=1)
+    obj.env_import(env0)
+    e_lib, g_lib = obj.energy_grad(h, ns, 1)
+    obj.close()
+    e_ref, g_ref = og.energy_and_grad(A_np, env0_np, chi, chi, ns, h)
+    gn = g.detach().cpu().numpy()
+    assert float(e) == e_lib
+    assert torch.equal(g, g_lib)
+    assert abs(float(e) - e_ref) <= 1e-10 * abs(e_ref)
+    assert np.linalg.norm(gn - g_ref) <= 1e-8 * np.linalg.norm(g_ref)
+    assert torch.allclose(g3, 3.0 * g, rtol=1e-14, atol=0)
+
+
+def test_ctm_energy_autograd_options_and_warm_start():
+    """CtmEnergy passes chi_I < chi_E, a separate vertical Hamiltonian and the
+    App. B alternative yellow / red flag through to the library (same result
+    as SplitCTM.energy_grad with those options), and a state dict carries the
+    environment from one call to the next (the second call starts where the
+    first ended)."""
+    A_np = inp.peps_gaussian(13, 1, 1, 2, 2)
+    chiE, chiI, ns = 6, 4, 2
+    h = inp.heisenberg_h_rotated()
+    hv = 0.5 * inp.heisenberg_h_rotated()
+    _say("CtmEnergy options d2 chiE6 chiI4 alt_yr")
+    A = torch.tensor(A_np, device=DEV, requires_grad=True)
+    state = {}
+    e1 = b.ctm_energy(A, h, chiE, ns, chi_I=chiI, h_v=hv, alt_yr=True, state=state)
+    (g1,) = torch.autograd.grad(e1, A)
+    env_after_1 = state["env"].clone()
+    e2 = b.ctm_energy(A, h, chiE, ns, chi_I=chiI, h_v=hv, alt_yr=True, state=state)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chiE, chiI, prec="fp64", with_grad=True, n_sweeps=ns,
+                     ckpt_every=1, alt_yr=True)
+    e_lib, g_lib = obj.energy_grad(h, ns, 1, h_v=hv)
+    obj.env_import(env_after_1)
+    e_lib2, _ = obj.energy_grad(h, ns, 1, h_v=hv)
+    obj.close()
+    assert float(e1) == e_lib and torch.equal(g1, g_lib)
+    assert float(e2) == e_lib2
+
+
 @pytest.fixture(scope="module")
 def converged_env_d2_chi8():
     """The oracle's own environment of the d2_D2_chi8 workload after 20
