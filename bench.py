@@ -89,6 +89,11 @@ def parse():
                          "of those of App. A")
     ap.add_argument("--half-teal", action="store_true",
                     help="the teal half projectors of App. B (left halves of the patch) instead of the full ones")
+    ap.add_argument("--prec", default=None, help="contraction precision of the timed steps (default: the workload's)")
+    ap.add_argument("--legs", default="fp64,bf16x3,bf16x6",
+                    help="other contraction precisions timed beside the headline on the same start environment "
+                         "(comma-separated; the FP64 leg is the reference of the error columns); empty: none")
+    ap.add_argument("--leg-steps", type=int, default=2, help="timed steps of each leg (after one warmup step)")
     return ap.parse_args()
 
 
@@ -189,6 +194,44 @@ def scaling(args) -> None:
           flush=True)
 
 
+def time_steps(obj, h, args, steps):
+    """`steps` energy + gradient evaluations from the context's start
+    environment; returns (E, dE/dA, seconds)."""
+    import torch
+    e = dA = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        e, dA = obj.energy_grad(h, args.grad_sweeps, args.ckpt)
+        say(f"{obj.prec_name} timed step {i} done")
+    torch.cuda.synchronize()
+    return e, dA, time.perf_counter() - t0
+
+
+def time_sweeps(obj, flat, n):
+    """Forward-only sweeps/s from the environment `flat`."""
+    import torch
+    obj.env_import(flat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obj.sweep(n)
+    torch.cuda.synchronize()
+    return n / (time.perf_counter() - t0)
+
+
+def contraction_mfma(timing: dict, prec: str) -> dict:
+    """MFMA figure of the contraction GEMMs of precision `prec`: their
+    algorithmic flops (2 M N K per product) over their kernel time, against
+    the dense peak of the products they issue."""
+    key = {"fp64": "gemm_fp64", "fp32": "gemm_fp32", "bf16x3": "gemm_bf16x3", "bf16x6": "gemm_bf16x6"}[prec]
+    ms, launches, flops, nbytes = timing[key]
+    peak, basis = MFMA_PEAKS[key]
+    tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"kernel": key, "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak, "peak_basis": basis,
+            "ms": ms, "launches": int(launches),
+            "arith_intensity_flop_per_byte": flops / nbytes if nbytes else None}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -217,47 +260,66 @@ def main():
         return
     w = inp.WORKLOADS[WORKLOAD]
     chi = w["chi"]
+    prec = args.prec or w["prec"]
     dev = torch.device("cuda:0")
     A = torch.tensor(inp.workload_peps(WORKLOAD), device=dev)
     h = inp.workload_h(WORKLOAD)
-    obj = b.SplitCTM(A, chi, chi, prec=w["prec"], with_grad=True, n_sweeps=args.grad_sweeps,
-                     ckpt_every=args.ckpt, alt_yr=args.alt_yr, half_teal=args.half_teal)
 
+    def context(p):
+        o = b.SplitCTM(A, chi, chi, prec=p, with_grad=True, n_sweeps=args.grad_sweeps, ckpt_every=args.ckpt,
+                       alt_yr=args.alt_yr, half_teal=args.half_teal)
+        o.prec_name = p
+        return o
+
+    obj = context(prec)
     # untimed: converge the start environment (an optimisation step starts from
-    # the previous step's environment)
-    st, n, delta = obj.sweep(args.pre_sweeps)
-    obj.env_import(obj.env_export())
+    # the previous step's environment); every timed step and every leg starts
+    # from this same environment
+    st, n, delta = obj.sweep(args.pre_sweeps, 0.0)
+    flat0 = obj.env_export()
+    obj.env_import(flat0)
     torch.cuda.synchronize()
-    say(f"start environment: {n} sweeps, corner-spectrum change {delta:.2e}")
+    say(f"start environment: {n} {prec} sweeps from the identity boundary, corner-spectrum change over the last "
+        f"one {delta:.2e}")
 
     for i in range(args.warmup):
         obj.energy_grad(h, args.grad_sweeps, args.ckpt)
         say(f"warmup step {i} done")
-    obj.env_import(obj.env_export())
-    torch.cuda.synchronize()
-
     obj.kernel_timing_enable(True, stride=args.timing_stride)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e = None
-    for i in range(args.steps):
-        e, dA = obj.energy_grad(h, args.grad_sweeps, args.ckpt)
-        say(f"timed step {i} done")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    e, dA, dt = time_steps(obj, h, args, args.steps)
     timing = obj.kernel_timing()
     obj.kernel_timing_enable(False)
-    dt = t1 - t0
     evals_per_s = args.steps / dt
-    gnorm = float(dA.norm())
-
-    # forward-only sweeps/s on the same context
-    torch.cuda.synchronize()
-    s0 = time.perf_counter()
-    obj.sweep(args.fwd_sweeps)
-    torch.cuda.synchronize()
-    sweeps_per_s = args.fwd_sweeps / (time.perf_counter() - s0)
+    sweeps_per_s = time_sweeps(obj, flat0, args.fwd_sweeps)
     say(f"forward sweeps: {sweeps_per_s:.3f} sweeps/s")
+    obj.close()
+    del obj
+    torch.cuda.empty_cache()
+
+    # the other precisions on the same start environment; FP64 is the
+    # reference of the error columns (it matches the oracle to 1e-10)
+    legs = {prec: {"evals_per_s": evals_per_s, "ms_per_step": 1e3 * dt / args.steps, "sweeps_per_s": sweeps_per_s,
+                   "energy": e, "_g": dA}}
+    for p in [x for x in args.legs.split(",") if x and x != prec]:
+        o = context(p)
+        o.env_import(flat0)
+        o.energy_grad(h, args.grad_sweeps, args.ckpt)
+        say(f"{p} warmup step done")
+        ep, gp, dtp = time_steps(o, h, args, args.leg_steps)
+        legs[p] = {"evals_per_s": args.leg_steps / dtp, "ms_per_step": 1e3 * dtp / args.leg_steps,
+                   "sweeps_per_s": time_sweeps(o, flat0, max(1, args.fwd_sweeps // 2)), "energy": ep, "_g": gp}
+        o.close()
+        del o
+        torch.cuda.empty_cache()
+    ref = legs.get("fp64")
+    for p, v in legs.items():
+        if ref is not None:
+            v["energy_rel_err_vs_fp64"] = abs(v["energy"] - ref["energy"]) / abs(ref["energy"])
+            v["grad_rel_err_vs_fp64"] = float((v["_g"] - ref["_g"]).norm() / ref["_g"].norm())
+            v["speedup_vs_fp64"] = v["evals_per_s"] / ref["evals_per_s"]
+    gnorm = float(dA.norm())
+    for v in legs.values():
+        v.pop("_g")
 
     dom = max(timing, key=lambda k: timing[k][0])
     ms, launches, flops, nbytes = timing[dom]
@@ -288,20 +350,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3",
+        "dtype": prec,
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "cell": "2x2", "p": 2, "D": 8, "chi_E": chi, "chi_I": chi,
                    "sweeps_per_eval": args.grad_sweeps, "ckpt_every": args.ckpt,
-                   "pre_sweeps": args.pre_sweeps,
+                   "pre_sweeps": args.pre_sweeps, "start_env_delta": delta,
                    "projectors": projectors_label(args)},
         "sweeps_per_s": sweeps_per_s,
         "energy": e,
         "grad_norm": gnorm,
+        "mfma_frac": contraction_mfma(timing, prec),
+        "precision_legs": legs,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    obj.close()
 
 
 if __name__ == "__main__":

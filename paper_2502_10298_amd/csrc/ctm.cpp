@@ -1063,7 +1063,7 @@ ctm_status ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, d
       E.ar.release(mk);
     }
     ++done;
-    c->spec_current = false;
+    if (!measure) c->spec_current = false;   // spec_prev no longer belongs to the current environment
     if (measure) {
       d = corner_delta(c);
       if (!(d == d)) {

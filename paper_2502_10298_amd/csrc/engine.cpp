@@ -217,6 +217,28 @@ Ten Engine::normalize(const Ten& A) {
 // ---------------------------------------------------------------------------
 void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten& A, long offA, long lda,
                   const Ten& B, long offB, long ldb, double beta, const Ten& C, long offC, long ldc) {
+  // SPLITCTM_TRACE >= 2: every product synchronised and timed on the host,
+  // with its shape and route (diagnostics; distorts the run's own timing)
+  static const bool timed = [] {
+    const char* e = getenv("SPLITCTM_TRACE");
+    return e && atoi(e) >= 2;
+  }();
+  if (!timed || dry) {
+    gemm_route(tA, tB, M, N, K, alpha, A, offA, lda, B, offB, ldb, beta, C, offC, ldc);
+    return;
+  }
+  check(hipStreamSynchronize(s));
+  const auto t0 = std::chrono::steady_clock::now();
+  const char* route = gemm_route(tA, tB, M, N, K, alpha, A, offA, lda, B, offB, ldb, beta, C, offC, ldc);
+  check(hipStreamSynchronize(s));
+  const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  fprintf(stderr, "[gemm] route=%s dt=%d tA=%d tB=%d M=%d N=%d K=%d lda=%ld ldb=%ld ldc=%ld beta=%g us=%.1f\n", route,
+          C.dt, (int)tA, (int)tB, M, N, K, lda, ldb, ldc, beta, us);
+}
+
+const char* Engine::gemm_route(bool tA, bool tB, int M, int N, int K, double alpha, const Ten& A, long offA,
+                               long lda, const Ten& B, long offB, long ldb, double beta, const Ten& C, long offC,
+                               long ldc) {
   flops_gemm += 2L * M * N * K;
   // large BF16X3 products: operands split once into bf16 planes (scratch from the arena)
   if (C.dt == F32 && prec == Prec::BF16X3) {
@@ -229,7 +251,7 @@ void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten
                               (float)beta, C.f32() + offC, ldc, w));
       if (!w && !dry) status = 2;   // workspace exhausted
       ar.release(mk);
-      return;
+      return "presplit";
     }
   }
   // Split-K (long K, few output tiles): the scratch for the slices comes from the arena
@@ -246,10 +268,10 @@ void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten
                               A.f32() + offA, lda, B.f32() + offB, ldb, (float)beta, C.f32() + offC, ldc, P.f32()));
     }
     ar.release(mk);
-    return;
+    return "splitk";
   }
-  if (dry || !ok()) return;
-  if (M <= 0 || N <= 0) return;
+  if (dry || !ok()) return "none";
+  if (M <= 0 || N <= 0) return "none";
   if (K <= 0) {   // C = beta C
     if (beta == 0.0) {
       // zero the M x N block row by row (contiguous when ldc == N)
@@ -260,16 +282,7 @@ void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten
           check(fill_f32(s, C.f32() + offC, 0.f, (long)M * N));
       }
     }
-    return;
-  }
-  static const bool timed = [] {
-    const char* e = getenv("SPLITCTM_TRACE");
-    return e && atoi(e) >= 2;
-  }();
-  std::chrono::steady_clock::time_point t0;
-  if (timed) {
-    check(hipStreamSynchronize(s));
-    t0 = std::chrono::steady_clock::now();
+    return "none";
   }
   if (C.dt == F64)
     check(gemm_f64(s, tA, tB, M, N, K, alpha, A.f64() + offA, lda, 0, B.f64() + offB, ldb, 0, beta,
@@ -277,12 +290,7 @@ void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten
   else
     check(gemm_f32(s, prec, tA, tB, M, N, K, (float)alpha,
                    A.f32() + offA, lda, 0, B.f32() + offB, ldb, 0, (float)beta, C.f32() + offC, ldc, 0, 1));
-  if (timed) {
-    check(hipStreamSynchronize(s));
-    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-    fprintf(stderr, "[gemm] dt=%d tA=%d tB=%d M=%d N=%d K=%d lda=%ld ldb=%ld ldc=%ld us=%.1f\n", C.dt, (int)tA, (int)tB,
-            M, N, K, lda, ldb, ldc, us);
-  }
+  return "plain";
 }
 
 // ---------------------------------------------------------------------------
@@ -800,6 +808,18 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
       check(hipStreamSynchronize(s));
       const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       fprintf(stderr, "[svd] n=%ld batch=%ld sweeps=%d %.1f ms\n", n, jobs[n], sweeps, ms);
+      // how far each spectrum reaches: counts of s > 10^-k s_1
+      std::vector<double> hs((size_t)jobs[n] * n);
+      check(hipMemcpy(hs.data(), jS[n].p, sizeof(double) * hs.size(), hipMemcpyDeviceToHost));
+      for (long b = 0; b < jobs[n]; ++b) {
+        const double* S = hs.data() + b * n;
+        int c[8] = {0};
+        for (long i = 0; i < n; ++i)
+          for (int k = 0; k < 8; ++k)
+            if (S[i] > std::pow(10.0, -2.0 * (k + 1)) * S[0]) ++c[k];
+        fprintf(stderr, "[spectrum] n=%ld entry=%ld above 1e-2..1e-16: %d %d %d %d %d %d %d %d  s_chi+1/s_chi=%.4f\n", n, b,
+                c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7], n > 128 && S[127] > 0 ? S[128] / S[127] : 0.0);
+      }
     }
   }
   // low-rank route: U = Q_L U', V = Q_R V' in the first r0 columns; the rest (and S beyond r0) are zero

@@ -200,6 +200,9 @@ struct Engine {
   void permute_into(const Ten& A, const std::string& spec, const Ten& out, bool accumulate);
   void gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten& A, long offA, long lda,
             const Ten& B, long offB, long ldb, double beta, const Ten& C, long offC, long ldc);
+  // the product on its route (pre-split BF16X3, split-K or plain); returns the route's name
+  const char* gemm_route(bool tA, bool tB, int M, int N, int K, double alpha, const Ten& A, long offA, long lda,
+                         const Ten& B, long offB, long ldb, double beta, const Ten& C, long offC, long ldc);
   void add_into(const Ten& src, const Ten& dst);         // dst += src (same dtype/size)
 
   // ---- reverse pass ----

@@ -568,6 +568,14 @@ __global__ void svd_scatter_kernel(const double* Gt_all, const double* Vt_all, c
   }
 }
 
+// Y <- 1.5 I - 0.5 Y for batch n x n matrices at stride sY
+__global__ void ns_shift_kernel(double* Y_all, int n, long sY) {
+  double* Y = Y_all + blockIdx.y * sY;
+  const long tot = (long)n * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
+    Y[e] = ((e / n) == (e % n) ? 1.5 : 0.0) - 0.5 * Y[e];
+}
+
 hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, double* S, double* V, void* work,
                    int max_sweeps, double tol, int* host_flags, int* sweeps_out, const double* V0) {
   if (n < 1 || n > 4096) return hipErrorInvalidValue;   // the column ranks stage n norms in LDS
@@ -672,6 +680,28 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
     int g = (int)std::min<long>((tot + 255) / 256, 8192);
     hipLaunchKernelGGL(svd_scatter_kernel, dim3(g, batch), dim3(256), 0, s, Gt, Vt, norms, rank, n, L.np, L.sG, L.sV,
                        U, S, V);
+  }
+  // V is the product of every rotation of every sweep: each is orthogonal to
+  // rounding, but their product drifts (~1e-13 after ten sweeps at n ~ 1000),
+  // while U = G / |G| is orthogonal to the stopping tolerance.  The reverse
+  // pass of a truncated SVD with a strongly graded spectrum (s_k / s_1 down to
+  // 1e-7) turns that drift into a gradient error of about drift * s_1 / s_k,
+  // so V is brought back to working orthogonality by one Newton-Schulz step
+  // V <- V (3 I - V^T V) / 2 (the defect d becomes ~ d^2; the buffers of the
+  // sweeps, free now, hold V^T V and the product).
+  {
+    double* Y = Vt2;   // n x n at stride sV >= n^2
+    double* Vn = Gt2;  // n x n at stride sG >= n^2
+    const long nn = (long)n * n;
+    err = gemm_f64(s, true, false, n, n, n, 1.0, V, n, nn, V, n, nn, 0.0, Y, n, L.sV, batch);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(ns_shift_kernel, dim3((int)std::min<long>((nn + 255) / 256, 4096), batch), dim3(256), 0, s, Y,
+                       n, L.sV);
+    err = gemm_f64(s, false, false, n, n, n, 1.0, V, n, nn, Y, n, L.sV, 0.0, Vn, n, L.sG, batch);
+    if (err != hipSuccess) return err;
+    err = hipMemcpy2DAsync(V, sizeof(double) * nn, Vn, sizeof(double) * L.sG, sizeof(double) * nn, batch,
+                           hipMemcpyDeviceToDevice, s);
+    if (err != hipSuccess) return err;
   }
   if (sweeps_out) *sweeps_out = sweeps;
   return hipGetLastError();

@@ -123,9 +123,10 @@ def test_headline_gradient_scale_invariance(headline_env):
 
 @pytest.fixture(scope="module")
 def headline_column_oracle(headline_env):
-    """The oracle's projectors of column 0 of the left move (both cuts) and
-    its new left environment of column 1, from the GPU's environment after
-    three BF16x3 sweeps (about 20 s on the host cores)."""
+    """The oracle's projectors of column 0 of the left move (both cuts), its
+    new left environment of column 1 and the energy of the vertical bond of
+    site [0, 1] after that column, from the GPU's environment after three
+    BF16x3 sweeps (about 30 s on the host cores)."""
     A_np, flat, _, _ = headline_env
     w = inp.WORKLOADS[W]
     chi, D = w["chi"], w["D"]
@@ -136,19 +137,24 @@ def headline_column_oracle(headline_env):
         G, Y, TH, R, _ = sc.column_projectors(env, A, 2, 2, 0, chi, chi)
         _say("oracle: column 0 of the left move")
         sc.left_move_column(env, A, 2, 2, 0, chi, chi)
+        _say("oracle: vertical bond of site [0, 1] after the column")
+        e01 = float(sc.bond_value(sc.rdm_vertical(env, A, 0, 1, 2, 2), inp.workload_h(W)))
     return {"proj": {"green": G, "teal": TH, "yellow": Y, "red": R},
-            "new": {x: {k: env[(x, 1)][k].numpy() for k in ("C1", "T4k", "T4b", "C4")} for x in range(2)}}
+            "new": {x: {k: env[(x, 1)][k].numpy() for k in ("C1", "T4k", "T4b", "C4")} for x in range(2)},
+            "bond_v01": e01}
 
 
-def _column_on_gpu(A_np, flat, prec):
+def _column_on_gpu(A_np, flat, prec, energy=False):
     w = inp.WORKLOADS[W]
     obj = b.SplitCTM(torch.tensor(A_np, device=DEV), w["chi"], w["chi"], prec=prec)
     obj.env_import(flat)
     proj = [obj.projectors(0, x, 0) for x in range(2)]
     obj.move_column(0, 0)
     out = obj.env_export().cpu().numpy()
+    bonds = obj.energy(inp.workload_h(W))[1] if energy else None
     obj.close()
-    return proj, inp.unpack_env(out, 2, 2, w["D"], w["chi"], w["chi"])
+    env = inp.unpack_env(out, 2, 2, w["D"], w["chi"], w["chi"])
+    return (proj, env, bonds) if energy else (proj, env)
 
 
 def test_headline_column_parity_fp64(headline_env, headline_column_oracle):
@@ -157,16 +163,20 @@ def test_headline_column_parity_fp64(headline_env, headline_column_oracle):
     pairs of both cuts of column 0 of the left move (Fig. proj_plots_green,
     App. A) and the new C1, T4k, T4b, C4 of both rows of column 1 (Eqs.
     splitCTMRG_C1 / _C4 / _Tket / _Tbra) equal the oracle's element by
-    element.  This runs the n = 1024 batched Jacobi, the 2048-row Householder
-    QRs of the rank-limited route and the split-K contractions at their real
-    shapes.  Projectors to 1e-8 and environment tensors to 1e-9 of their
-    largest entry (sign-fixed columns; the kept singular values are
-    separated, so the columns are unique)."""
+    element, and the energy of the vertical bond of site [0, 1], which these
+    new tensors enter, agrees to 1e-10 relative.  This runs the n = 1024
+    batched Jacobi, the 2048-row Householder QRs of the rank-limited route
+    and the split-K contractions at their real shapes.
+    Element-wise bound 5e-8 of the largest entry: the columns are sign-fixed,
+    but a column of a singular pair at a small gap is fixed only to about
+    eps |M| / gap, in the oracle's LAPACK SVD as in the Jacobi; the smallest
+    relative gaps of the kept spectra here leave ~1e-8."""
     A_np, flat, _, _ = headline_env
     ref = headline_column_oracle
+    w = inp.WORKLOADS[W]
     _say("headline: FP64 projectors and one column of the left move")
-    proj, new = _column_on_gpu(A_np, flat, "fp64")
-    worst_p = worst_e = 0.0
+    proj, new, bonds = _column_on_gpu(A_np, flat, "fp64", energy=True)
+    errs = {}
     for x in range(2):
         P, _ = proj[x]
         for nm, prs in ref["proj"].items():
@@ -175,33 +185,41 @@ def test_headline_column_parity_fp64(headline_env, headline_column_oracle):
             for j, side in ((0, "_T"), (1, "_B")):
                 r = pr[j].numpy()
                 got = P[nm + side].cpu().numpy()[..., :k].reshape(r.shape)
-                err = float(np.abs(got - r).max() / np.abs(r).max())
-                worst_p = max(worst_p, err)
-                assert err <= 1e-8, (x, nm, side, err)
+                errs[("proj", x, nm + side)] = float(np.abs(got - r).max() / np.abs(r).max())
             tail = P[nm + "_T"].cpu().numpy()[..., k:]
             assert tail.size == 0 or float(np.abs(tail).max()) == 0.0
         for t in ("C1", "T4k", "T4b", "C4"):
             r = ref["new"][x][t]
-            err = float(np.abs(new[(x, 1)][t] - r).max() / np.abs(r).max())
-            worst_e = max(worst_e, err)
-            assert err <= 1e-9, (x, t, err)
-    print(f"[result] headline column, FP64 vs oracle: projectors {worst_p:.1e}, new C1/T4k/T4b/C4 {worst_e:.1e}")
+            errs[("env", x, t)] = float(np.abs(new[(x, 1)][t] - r).max() / np.abs(r).max())
+    worst_p = max(v for k, v in errs.items() if k[0] == "proj")
+    worst_e = max(v for k, v in errs.items() if k[0] == "env")
+    e_ref = ref["bond_v01"]
+    e_gpu = float(bonds[0, 1, 1])
+    print(f"[result] headline column, FP64 vs oracle: projectors {worst_p:.1e}, new C1/T4k/T4b/C4 {worst_e:.1e}, "
+          f"vertical bond [0,1] {e_gpu:.15e} vs {e_ref:.15e}")
+    print("[result] per tensor:", {"/".join(map(str, k)): f"{v:.1e}" for k, v in errs.items()})
+    assert worst_p <= 5e-8 and worst_e <= 5e-8
+    assert abs(e_gpu - e_ref) <= 1e-10 * abs(e_ref)
 
 
 def test_headline_column_parity_bf16x3_and_bf16x6(headline_env, headline_column_oracle):
     """The same step with BF16x3 and BF16x6 contractions (FP64 projector
-    SVDs): the new C1, T4k, T4b, C4 against the FP64 oracle.  The error is
-    the contractions' own (2^-17 relative per BF16x3 product, near FP32
-    rounding for BF16x6) amplified by the conditioning of the truncated
-    subspaces; the bounds are 1e-3 (BF16x3) and 1e-4 (BF16x6) of the
-    largest entry, and the corner spectra, which do not depend on the
-    subspace's gauge, within 1e-4 (BF16x3) and 1e-5 (BF16x6) of the
-    largest singular value."""
+    SVDs) against the FP64 oracle, on what does not depend on the gauge of
+    the truncated subspaces: the singular values of the new corners C1 and
+    C4 of both rows, and the energy of the vertical bond of site [0, 1].
+    The contractions' rounding (2^-17 relative per BF16x3 product, FP32
+    rounding of the stored tensors for both) moves the spectra by about
+    that much of s_1 (Weyl); bounds 1e-5 s_1 (BF16x3) and 1e-6 s_1 (BF16x6),
+    and the bond energy 1e-6 |h|_2 (the bond value is ~1e-3 of |h|_2 for
+    these Gaussian tensors, a near-cancellation of its terms).  Element-wise
+    differences are printed only: a column of a near-degenerate pair turns
+    with a 1e-5 perturbation by that over the pair's gap."""
     A_np, flat, _, _ = headline_env
     ref = headline_column_oracle
-    for prec, etol, stol in (("bf16x3", 1e-3, 1e-4), ("bf16x6", 1e-4, 1e-5)):
+    hnorm = float(np.linalg.norm(inp.workload_h(W), 2))
+    for prec, stol in (("bf16x3", 1e-5), ("bf16x6", 1e-6)):
         _say(f"headline: one column of the left move, {prec}")
-        _, new = _column_on_gpu(A_np, flat, prec)
+        _, new, bonds = _column_on_gpu(A_np, flat, prec, energy=True)
         worst_e = worst_s = 0.0
         for x in range(2):
             for t in ("C1", "T4k", "T4b", "C4"):
@@ -211,17 +229,21 @@ def test_headline_column_parity_bf16x3_and_bf16x6(headline_env, headline_column_
                 s_ref = np.linalg.svd(ref["new"][x][t], compute_uv=False)
                 s_got = np.linalg.svd(new[(x, 1)][t], compute_uv=False)
                 worst_s = max(worst_s, float(np.abs(s_got - s_ref).max() / s_ref[0]))
-        print(f"[result] headline column, {prec} vs FP64 oracle: new tensors {worst_e:.1e}, corner spectra {worst_s:.1e}")
-        assert worst_e <= etol and worst_s <= stol, (prec, worst_e, worst_s)
+        eb = abs(float(bonds[0, 1, 1]) - ref["bond_v01"])
+        print(f"[result] headline column, {prec} vs FP64 oracle: corner spectra {worst_s:.1e} s_1, vertical bond "
+              f"[0,1] {eb:.1e} abs ({eb / hnorm:.1e} |h|), element-wise {worst_e:.1e}")
+        assert worst_s <= stol, (prec, worst_s)
+        assert eb <= 1e-6 * hnorm, (prec, eb)
 
 
 def test_headline_gradient_directional_finite_differences(headline_env):
     """The FP64 gradient of the headline workload (one sweep from the GPU's
     environment after three sweeps, then the energy) against fourth-order
-    central differences of the FP64 energy along two seeded random
-    directions d with |d| = |A| (step 1e-4): |fd - <g, d>| <= 1e-5 |<g, d>|.
-    Each difference runs the full-size path: n = 1024 Jacobi SVDs, 2048-row
-    QRs and the reverse pass through them."""
+    central differences of the FP64 energy along two seeded random unit
+    directions d (step 1e-4, and 1e-5 printed beside it):
+    |fd - <g, d>| <= 1e-5 |<g, d>|.  Each difference runs the full-size
+    path: n = 1024 Jacobi SVDs, 2048-row QRs and the reverse pass through
+    them."""
     A_np, flat, _, _ = headline_env
     w = inp.WORKLOADS[W]
     chi, h = w["chi"], inp.workload_h(W)
@@ -241,19 +263,20 @@ def test_headline_gradient_directional_finite_differences(headline_env):
         o.close()
         return e
 
+    def fd4(d, step):
+        f = [energy_at(A_np + t * step * d) for t in (1, -1, 2, -2)]
+        return (8.0 * (f[0] - f[1]) - (f[2] - f[3])) / (12.0 * step)
+
     rng = np.random.default_rng(2025)
-    step = 1e-4
     for k in range(2):
         d = rng.standard_normal(A_np.shape)
-        d *= np.linalg.norm(A_np) / np.linalg.norm(d)
-        f = []
-        for t in (1, -1, 2, -2):
-            _say(f"headline: FP64 energy at A + {t} h d{k}")
-            f.append(energy_at(A_np + t * step * d))
-        fd = (8.0 * (f[0] - f[1]) - (f[2] - f[3])) / (12.0 * step)
+        d /= np.linalg.norm(d)
         gd = float((g * d).sum())
-        print(f"[result] direction {k}: fd {fd:.12e}, <g, d> {gd:.12e}, rel {abs(fd - gd) / abs(gd):.1e}")
-        assert abs(fd - gd) <= 1e-5 * abs(gd)
+        _say(f"headline: FP64 energies along direction {k}, steps 1e-4 and 1e-5")
+        fa, fb = fd4(d, 1e-4), fd4(d, 1e-5)
+        print(f"[result] direction {k}: <g, d> {gd:.12e}, fd(1e-4) {fa:.12e} rel {abs(fa - gd) / abs(gd):.1e}, "
+              f"fd(1e-5) {fb:.12e} rel {abs(fb - gd) / abs(gd):.1e}")
+        assert abs(fa - gd) <= 1e-5 * abs(gd)
 
 
 # ---------------------------------------------------------------------------
@@ -282,8 +305,11 @@ def test_config_d2_D4_chi32_converged_parity():
     assert abs(n_gpu - n_ref) <= 1
     assert abs(e_gpu - e_ref) <= 1e-10 * abs(e_ref)
     # the FP32 leg: the corner spectra of FP32 tensors settle at the FP32
-    # rounding level, so the 1e-10 test is not reachable; the energy after
-    # the 50-sweep budget must be within 1e-6 of the oracle's
+    # rounding level, so the 1e-10 test is not reachable.  A relative error
+    # eps of the FP32-stored reduced density matrices moves a bond energy
+    # tr(rho h) / tr(rho) by up to 2 eps |h|_2 whatever its size, and this
+    # state's energy per site (-6e-3) is a near-cancellation of bond terms of
+    # order 0.1, so the bound is 1e-6 |h|_2 (relative error printed)
     _say(name, "GPU FP32, 50 sweeps")
     obj = b.SplitCTM(torch.tensor(A_np, device=DEV), w["chi"], w["chi"], prec="fp32")
     st32, n32, d32 = obj.sweep(w["sweeps"], w["tol"])
@@ -292,7 +318,7 @@ def test_config_d2_D4_chi32_converged_parity():
     print(f"[result] {name} FP32: {e32:.15e} ({n32} sweeps, delta reached {d32:.1e}), "
           f"rel err {abs(e32 - e_ref) / abs(e_ref):.1e}")
     assert st32 in (b.CTM_OK, b.CTM_ENOTCONV) and d32 < 1e-5
-    assert abs(e32 - e_ref) <= 1e-6 * abs(e_ref)
+    assert abs(e32 - e_ref) <= 1e-6 * float(np.linalg.norm(h, 2))
 
 
 def test_config_d2_D6_chi72_gradient_finite_differences():
@@ -398,8 +424,8 @@ def test_config_d2_D6_chi72_gradient_40_sweeps_checkpointed():
     after 40 sweeps from the identity boundary, dE/dA through all of them
     with checkpoints every 5 sweeps (8 blocks, each recomputed in the
     reverse pass).  FP64 gradient against second-order central differences
-    of the FP64 energy along two seeded directions (|d| = |A|, step 1e-4)
-    to 1e-5 relative; FP32 contractions against FP64: energy within 1e-6
+    of the FP64 energy along two seeded unit directions (step 1e-4) to 1e-5
+    relative; FP32 contractions against FP64: energy within 1e-6
     |h|_2 and gradient entries within 1e-4 of the largest (norm-wise error
     reported)."""
     name = "d2_D6_chi72_grad"
@@ -427,7 +453,7 @@ def test_config_d2_D6_chi72_gradient_40_sweeps_checkpointed():
     step = 1e-4
     for k in range(2):
         d = rng.standard_normal(A_np.shape)
-        d *= np.linalg.norm(A_np) / np.linalg.norm(d)
+        d /= np.linalg.norm(d)
         _say(name, f"central difference along direction {k}")
         fd = (energy_at(A_np + step * d) - energy_at(A_np - step * d)) / (2 * step)
         gd = float((g64 * d).sum())
