@@ -246,6 +246,24 @@ ctm_status ctm_kernel_timing_enable(ctm_ctx* ctx, int on);
 ctm_status ctm_kernel_timing(ctm_ctx* ctx, int kernel_class, double* ms, double* launches, double* flops,
                              double* bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * ctm_init, but the workspace is the library's own static device array of
+ * CTM_STATIC_SCRATCH_BYTES, one per GPU, held from the library's first use on
+ * that GPU until the process ends.  The caller still passes A (device) and
+ * keeps ownership of it and of every output buffer; nothing is allocated.
+ * The array serves one context per device at a time: a second call on a
+ * device whose array belongs to a live context (until its ctm_destroy) is
+ * CTM_EINVAL, as is a configuration whose ctm_workspace_size (forward calls)
+ * exceeds the array; calls with a larger transient need (e.g. ctm_energy_grad
+ * over long checkpoint blocks) fail with CTM_EINVAL as with too small a
+ * workspace.  The array keeps the last context's contents: nothing in it is
+ * assumed to start at zero.  The device is the one current at the call;
+ * CTM_EDEVICE if it cannot be queried. */
+#define CTM_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+ctm_status ctm_init_static(const ctm_config* cfg, const double* A_dev, const double* boundary_vec_host,
+                           void* hip_stream, ctm_ctx** out);
+
 void ctm_destroy(ctm_ctx* ctx);
 const char* ctm_strerror(ctm_status s);
 

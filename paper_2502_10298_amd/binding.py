@@ -22,7 +22,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 INIT = {"identity": 0, "product": 1}
 
 EXPORTED = ("ctm_workspace_size", "ctm_init", "ctm_sweep", "ctm_projectors", "ctm_projectors_elems",
-            "ctm_move_column",
+            "ctm_move_column", "ctm_init_static",
             "ctm_energy", "ctm_energy_grad", "ctm_env_elems", "ctm_env_export", "ctm_env_import",
             "ctm_energy_hv", "ctm_energy_grad_hv", "ctm_last_stats", "ctm_debug_gemm_work_bytes", "ctm_debug_gemm", "ctm_debug_svd_work_bytes", "ctm_debug_svd", "ctm_debug_qr_work_bytes", "ctm_debug_qr",
             "ctm_kernel_timing_enable", "ctm_kernel_timing", "ctm_destroy", "ctm_strerror")
@@ -59,6 +59,7 @@ def lib() -> ctypes.CDLL:
     sig = {
         "ctm_workspace_size": (I, [cfgp, I, I, I, ctypes.POINTER(S)]),
         "ctm_init": (I, [cfgp, P, P, P, S, P, ctypes.POINTER(P)]),
+        "ctm_init_static": (I, [cfgp, P, P, P, ctypes.POINTER(P)]),
         "ctm_sweep": (I, [P, I, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
         "ctm_projectors": (I, [P, I, I, I, P, P]),
         "ctm_projectors_elems": (S, [cfgp]),
@@ -124,20 +125,25 @@ class SplitCTM:
 
     A: torch FP64 tensor [Lx, Ly, p, D, D, D, D] on the GPU (copied at init).
     alt_yr / half_teal: the alternative yellow / red projectors and the teal
-    half projectors of App. B."""
+    half projectors of App. B.  static_workspace: the context works in the
+    library's static device array (ctm_init_static) and no workspace is
+    allocated here."""
 
     def __init__(self, A, chi_E, chi_I=None, prec="fp64", init="identity", boundary=None,
                  with_grad=False, n_sweeps=0, ckpt_every=1, cutoff=1e-12, adj_eps=1e-12,
-                 workspace_bytes=None, stream=None, alt_yr=False, half_teal=False):
+                 workspace_bytes=None, stream=None, alt_yr=False, half_teal=False, static_workspace=False):
         self.torch = torch
         if A.dtype != torch.float64 or not A.is_cuda or A.dim() != 7:
             raise ValueError("A must be a CUDA float64 tensor [Lx, Ly, p, D, D, D, D]")
         Lx, Ly, p, D = A.shape[:4]
         self.cfg = make_config(Lx, Ly, p, D, chi_E, chi_I if chi_I is not None else chi_E, prec, init,
                                cutoff, adj_eps, alt_yr, half_teal)
-        need = workspace_size(self.cfg, with_grad, n_sweeps, ckpt_every)
-        self.ws_bytes = int(workspace_bytes) if workspace_bytes is not None else need
-        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=A.device)
+        if static_workspace:
+            self.ws_bytes, self.ws = 0, None
+        else:
+            need = workspace_size(self.cfg, with_grad, n_sweeps, ckpt_every)
+            self.ws_bytes = int(workspace_bytes) if workspace_bytes is not None else need
+            self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=A.device)
         self.stream = stream
         self.A = A.contiguous()
         bvec = None
@@ -145,10 +151,14 @@ class SplitCTM:
             self._bvec = (ctypes.c_double * D)(*[float(v) for v in np.asarray(boundary, dtype=np.float64)])
             bvec = ctypes.cast(self._bvec, ctypes.c_void_p)
         h = ctypes.c_void_p()
-        st = lib().ctm_init(ctypes.byref(self.cfg), _ptr(self.A), bvec, _ptr(self.ws), ctypes.c_size_t(self.ws_bytes),
-                            _stream_ptr(torch, stream), ctypes.byref(h))
+        if static_workspace:
+            st = lib().ctm_init_static(ctypes.byref(self.cfg), _ptr(self.A), bvec, _stream_ptr(torch, stream),
+                                       ctypes.byref(h))
+        else:
+            st = lib().ctm_init(ctypes.byref(self.cfg), _ptr(self.A), bvec, _ptr(self.ws),
+                                ctypes.c_size_t(self.ws_bytes), _stream_ptr(torch, stream), ctypes.byref(h))
         if st != CTM_OK:
-            raise CtmError(st, "ctm_init")
+            raise CtmError(st, "ctm_init_static" if static_workspace else "ctm_init")
         self.h = h
         self.env_elems = lib().ctm_env_elems(ctypes.byref(self.cfg))
 

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -57,7 +58,24 @@ struct ctm_ctx {
   double last_flops = 0, last_sweeps = 0;
   bool timing = false;     // HIP-event timing of the GEMM and Jacobi launches
   KernelTimer timer;
+  int static_device = -1;  // >= 0: the workspace is that device's static scratch array
 };
+
+// ---------------------------------------------------------------------------
+// Static device scratch for callers that cannot allocate (ctm_init_static).
+// Each GPU the library runs on holds its own copy for the life of the process.
+// In host code `scratch` is only a handle: its device address is looked up
+// once per device with hipGetSymbolAddress and kept in static_ptr.
+// ---------------------------------------------------------------------------
+static constexpr size_t kStaticScratchBytes = CTM_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex static_mu;
+void* static_ptr[kMaxDevices] = {};
+bool static_busy[kMaxDevices] = {};
+}  // namespace
 
 namespace {
 
@@ -1041,7 +1059,41 @@ ctm_status ctm_init(const ctm_config* cfg, const double* A_dev, const double* bv
   return CTM_OK;
 }
 
-void ctm_destroy(ctm_ctx* c) { delete c; }
+ctm_status ctm_init_static(const ctm_config* cfg, const double* A_dev, const double* bvec, void* stream,
+                           ctm_ctx** out) {
+  if (!out) return CTM_EINVAL;
+  *out = nullptr;
+  ctm_status st = validate(cfg);
+  if (st != CTM_OK || !A_dev) return CTM_EINVAL;
+  if (cfg->init == CTM_INIT_PRODUCT && !bvec) return CTM_EINVAL;
+  // the configuration's workspace (dry run, no device memory) must fit the array
+  size_t need = 0;
+  st = ctm_workspace_size(cfg, 0, 0, 1, &need);
+  if (st != CTM_OK) return st;
+  if (need > kStaticScratchBytes) return CTM_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CTM_EDEVICE;
+  std::lock_guard<std::mutex> lock(static_mu);
+  if (static_busy[dev]) return CTM_EINVAL;   // the device's array belongs to a live context
+  if (!static_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CTM_EDEVICE;
+    static_ptr[dev] = p;
+  }
+  st = ctm_init(cfg, A_dev, bvec, static_ptr[dev], kStaticScratchBytes, stream, out);
+  if (st != CTM_OK) return st;
+  (*out)->static_device = dev;
+  static_busy[dev] = true;
+  return CTM_OK;
+}
+
+void ctm_destroy(ctm_ctx* c) {
+  if (c && c->static_device >= 0) {
+    std::lock_guard<std::mutex> lock(static_mu);
+    static_busy[c->static_device] = false;
+  }
+  delete c;
+}
 
 ctm_status ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, double* delta) {
   if (!c || max_sweeps < 0) return CTM_EINVAL;
