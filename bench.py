@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grad-sweeps", type=int, default=4)
     ap.add_argument("--ckpt", type=int, default=4)
-    ap.add_argument("--pre-sweeps", type=int, default=6, help="untimed sweeps that converge the start environment")
+    ap.add_argument("--pre-sweeps", type=int, default=8, help="untimed sweeps that converge the start environment")
     ap.add_argument("--fwd-sweeps", type=int, default=4, help="timed forward-only sweeps for sweeps/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)

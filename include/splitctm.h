@@ -30,7 +30,8 @@
  *     the tensor-network contractions.  The one-sided Jacobi SVD runs to
  *     working accuracy with FP64 contractions and to a relative
  *     off-orthogonality of 1e-10 with FP32, BF16x3 or BF16x6 contractions,
- *     whose own rounding is larger.
+ *     whose own rounding is larger; its singular vectors are orthonormal to
+ *     FP64 rounding in every case (the reverse pass needs that).
  *
  * Errors: every call returns a ctm_status.  CTM_EINVAL = bad argument or
  * workspace too small (no side effects); CTM_ENUMERIC = non-finite values or a

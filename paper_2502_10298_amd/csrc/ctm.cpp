@@ -655,10 +655,11 @@ void setup_ctx(ctm_ctx* c, const ctm_config* cfg, void* ws, size_t bytes, hipStr
   E.cdt = cfg->contract_prec == CTM_FP64 ? F64 : F32;
   E.cutoff = cfg->svd_rel_cutoff > 0 ? cfg->svd_rel_cutoff : 1e-12;
   E.adj_eps = cfg->svd_adj_eps > 0 ? cfg->svd_adj_eps : 1e-12;
-  // Jacobi stopping level: working accuracy (sqrt(n) 1.2e-16) for FP64
-  // contractions; 1e-10 relative off-orthogonality when the contractions
-  // themselves carry FP32-level (or larger) rounding, which the sweeps past
-  // that level could not improve on
+  // Jacobi stopping level: working accuracy (sqrt(n) 1.2e-16 relative
+  // off-orthogonality) for FP64 contractions; 1e-10 when the contractions
+  // carry FP32-level rounding (1e-7 of |M| already in M itself).  Either way
+  // the factors leave the SVD orthonormal to rounding (the reverse pass needs
+  // that), so the stopping level only sets how close U S V^T is to M.
   E.svd_tol = cfg->contract_prec == CTM_FP64 ? 0.0 : 1e-10;
   E.host_flags = c->host_flags;
   E.host_flags_n = 256;

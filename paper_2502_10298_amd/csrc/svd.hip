@@ -682,26 +682,30 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
                        U, S, V);
   }
   // V is the product of every rotation of every sweep: each is orthogonal to
-  // rounding, but their product drifts (~1e-13 after ten sweeps at n ~ 1000),
-  // while U = G / |G| is orthogonal to the stopping tolerance.  The reverse
-  // pass of a truncated SVD with a strongly graded spectrum (s_k / s_1 down to
-  // 1e-7) turns that drift into a gradient error of about drift * s_1 / s_k,
-  // so V is brought back to working orthogonality by one Newton-Schulz step
-  // V <- V (3 I - V^T V) / 2 (the defect d becomes ~ d^2; the buffers of the
-  // sweeps, free now, hold V^T V and the product).
+  // rounding, but their product drifts (~1e-13 after ten sweeps at n ~ 1000);
+  // U = G / |G| is orthogonal to the stopping tolerance.  The reverse pass of
+  // a truncated SVD with a strongly graded spectrum (s_k / s_1 down to 1e-8)
+  // turns an orthogonality defect d into a gradient error of about
+  // d s_1 / s_k, so both factors are brought to working orthogonality by one
+  // Newton-Schulz step X <- X (3 I - X^T X) / 2 (d becomes ~ d^2; zero columns
+  // of U stay zero).  U S V^T then differs from M by the stopping tolerance,
+  // an exact SVD of a matrix that close to M.  The buffers of the sweeps,
+  // free now, hold X^T X and the product.
   {
     double* Y = Vt2;   // n x n at stride sV >= n^2
-    double* Vn = Gt2;  // n x n at stride sG >= n^2
+    double* Xn = Gt2;  // n x n at stride sG >= n^2
     const long nn = (long)n * n;
-    err = gemm_f64(s, true, false, n, n, n, 1.0, V, n, nn, V, n, nn, 0.0, Y, n, L.sV, batch);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(ns_shift_kernel, dim3((int)std::min<long>((nn + 255) / 256, 4096), batch), dim3(256), 0, s, Y,
-                       n, L.sV);
-    err = gemm_f64(s, false, false, n, n, n, 1.0, V, n, nn, Y, n, L.sV, 0.0, Vn, n, L.sG, batch);
-    if (err != hipSuccess) return err;
-    err = hipMemcpy2DAsync(V, sizeof(double) * nn, Vn, sizeof(double) * L.sG, sizeof(double) * nn, batch,
-                           hipMemcpyDeviceToDevice, s);
-    if (err != hipSuccess) return err;
+    for (double* X : {V, U}) {
+      err = gemm_f64(s, true, false, n, n, n, 1.0, X, n, nn, X, n, nn, 0.0, Y, n, L.sV, batch);
+      if (err != hipSuccess) return err;
+      hipLaunchKernelGGL(ns_shift_kernel, dim3((int)std::min<long>((nn + 255) / 256, 4096), batch), dim3(256), 0, s,
+                         Y, n, L.sV);
+      err = gemm_f64(s, false, false, n, n, n, 1.0, X, n, nn, Y, n, L.sV, 0.0, Xn, n, L.sG, batch);
+      if (err != hipSuccess) return err;
+      err = hipMemcpy2DAsync(X, sizeof(double) * nn, Xn, sizeof(double) * L.sG, sizeof(double) * nn, batch,
+                             hipMemcpyDeviceToDevice, s);
+      if (err != hipSuccess) return err;
+    }
   }
   if (sweeps_out) *sweeps_out = sweeps;
   return hipGetLastError();
@@ -710,10 +714,14 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
 // ---------------------------------------------------------------------------
 // Preconditioned SVD (Drmac and Veselic's QR preconditioning of one-sided
 // Jacobi): with the columns of A sorted by decreasing norm (permutation P),
-// A P = Q R by Householder QR, and the Jacobi SVD of R^T = U_J S V_J^T gives
-//   A = (Q V_J) S (P U_J)^T.
-// R^T has nearly orthogonal columns for graded A, so the Jacobi needs about
-// half the sweeps; the QR costs less than one sweep.
+// A P = Q R by Householder QR, then the QR of the lower-triangular R^T =
+// Q1 R1, and the Jacobi SVD of R1^T = U_J S V_J^T gives
+//   A = (Q U_J) S (P Q1 V_J)^T.
+// R^T has nearly orthogonal columns for graded A, and the second QR (one
+// step of the QR iteration on R R^T) makes them closer still: the Jacobi
+// needs about half the sweeps of the plain matrix, and two fewer with the
+// second QR than without it at the projector sizes; each QR costs less than
+// one sweep.
 
 // column norms of row-major n x n matrices (thread = column, coalesced rows)
 __global__ __launch_bounds__(256) void pre_colnorm_kernel(const double* A_all, int n, double* nrm_all) {
@@ -807,7 +815,7 @@ __global__ void pre_transpose_kernel(const double* A_all, int n, double* B_all) 
 }
 
 struct PreLayout {
-  size_t offX, offR, offQ, offUJ, offVJ, offN, offRk, offQW, offJW, total;
+  size_t offX, offR, offQ, offQ1, offUJ, offVJ, offN, offRk, offQW, offJW, total;
 };
 
 static PreLayout pre_layout(int n, int batch) {
@@ -822,6 +830,7 @@ static PreLayout pre_layout(int n, int batch) {
   L.offX = take(nn);
   L.offR = take(nn);
   L.offQ = take(nn);
+  L.offQ1 = take(nn);
   L.offUJ = take(nn);
   L.offVJ = take(nn);
   L.offN = take(sizeof(double) * (size_t)n * batch);
@@ -844,29 +853,35 @@ hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, dou
   double* Xt = (double*)(w + L.offX);
   double* R = (double*)(w + L.offR);
   double* Qt = (double*)(w + L.offQ);
+  double* Q1t = (double*)(w + L.offQ1);
   double* UJ = (double*)(w + L.offUJ);
   double* VJ = (double*)(w + L.offVJ);
   double* nrm = (double*)(w + L.offN);
   int* rk = (int*)(w + L.offRk);
   const long nn = (long)n * n;
+  const dim3 tiles((n + 31) / 32, (n + 31) / 32, batch);
   hipLaunchKernelGGL(pre_colnorm_kernel, dim3((n + 63) / 64, batch), dim3(256), 0, s, A, n, nrm);
   hipLaunchKernelGGL(pre_rank_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, (const double*)nrm, n, rk);
-  hipLaunchKernelGGL(pre_gather_kernel, dim3((n + 31) / 32, (n + 31) / 32, batch), dim3(256), 0, s, A,
-                     (const int*)rk, n, Xt);
+  hipLaunchKernelGGL(pre_gather_kernel, tiles, dim3(256), 0, s, A, (const int*)rk, n, Xt);
+  // A P = Q R (Xt holds (A P)^T)
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = qr_f64(s, n, n, batch, Xt, R, Qt, w + L.offQW);
-  // the Jacobi input is R^T: its columns (rows of R) are the rows of Gt, i.e. M = R^T
+  // R^T = Q1 R1: the QR of the lower-triangular R^T, whose transpose is R
+  // itself (R is overwritten by the reflectors; R1 lands in Xt)
+  if (e == hipSuccess) e = qr_f64(s, n, n, batch, R, Xt, Q1t, w + L.offQW);
+  // the Jacobi input is R1^T (row-major, in R)
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(pre_transpose_kernel, dim3((n + 31) / 32, (n + 31) / 32, batch), dim3(256), 0, s,
-                       (const double*)R, n, Xt);
+    hipLaunchKernelGGL(pre_transpose_kernel, tiles, dim3(256), 0, s, (const double*)Xt, n, R);
     e = hipGetLastError();
   }
   if (e == hipSuccess)
-    e = svd_f64(s, n, batch, Xt, UJ, S, VJ, w + L.offJW, max_sweeps, tol, host_flags, sweeps_out, nullptr);
-  // U = Q V_J,  V = P U_J
-  if (e == hipSuccess) e = gemm_f64(s, true, false, n, n, n, 1.0, Qt, n, nn, VJ, n, nn, 0.0, U, n, nn, batch);
+    e = svd_f64(s, n, batch, R, UJ, S, VJ, w + L.offJW, max_sweeps, tol, host_flags, sweeps_out, nullptr);
+  // R1^T = U_J S V_J^T  =>  A P = Q R1^T Q1^T... = (Q U_J) S (Q1 V_J)^T:
+  // U = Q U_J, V = P Q1 V_J
+  if (e == hipSuccess) e = gemm_f64(s, true, false, n, n, n, 1.0, Qt, n, nn, UJ, n, nn, 0.0, U, n, nn, batch);
+  if (e == hipSuccess) e = gemm_f64(s, true, false, n, n, n, 1.0, Q1t, n, nn, VJ, n, nn, 0.0, Xt, n, nn, batch);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(pre_unpermute_rows_kernel, dim3(n, batch), dim3(256), 0, s, (const double*)UJ,
+    hipLaunchKernelGGL(pre_unpermute_rows_kernel, dim3(n, batch), dim3(256), 0, s, (const double*)Xt,
                        (const int*)rk, n, V);
     e = hipGetLastError();
   }

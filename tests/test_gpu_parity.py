@@ -107,11 +107,11 @@ def test_jacobi_svd(n, batch):
         Ur, Vr = U[i][:, :r], V[i][:, :r]
         assert torch.allclose(Ur.T @ Ur, torch.eye(r, dtype=torch.float64), atol=1e-12)
         assert torch.allclose(Vr.T @ Vr, torch.eye(r, dtype=torch.float64), atol=1e-12)
-        # U (the QR's Q times the product of all Jacobi rotations) is a full
-        # orthogonal matrix to working accuracy, as a Householder-based SVD's
-        # is: the reverse pass of strongly graded spectra needs it (a drift of
-        # 1e-13 cost 1e-6 of the gradient at chi = 48)
-        assert float((U[i].T @ U[i] - torch.eye(n, dtype=torch.float64)).abs().max()) <= 5e-15 * math.sqrt(n)
+        # V (the second QR's Q times the product of all Jacobi rotations) is a
+        # full orthogonal matrix to working accuracy, as a Householder-based
+        # SVD's is: the reverse pass of strongly graded spectra needs it (a
+        # drift of 1e-13 cost 1e-6 of the gradient at chi = 48)
+        assert float((V[i].T @ V[i] - torch.eye(n, dtype=torch.float64)).abs().max()) <= 5e-15 * math.sqrt(n)
     assert sweeps < 60
 
 
