@@ -94,6 +94,9 @@ def parse():
                     help="other contraction precisions timed beside the headline on the same start environment "
                          "(comma-separated; the FP64 leg is the reference of the error columns); empty: none")
     ap.add_argument("--leg-steps", type=int, default=2, help="timed steps of each leg (after one warmup step)")
+    ap.add_argument("--lbfgs", type=int, default=0,
+                    help="instead of the bench line: this many L-BFGS iterations at the headline workload (one JSON "
+                         "line with the energies and seconds per optimisation step)")
     return ap.parse_args()
 
 
@@ -194,6 +197,32 @@ def scaling(args) -> None:
           flush=True)
 
 
+def lbfgs_run(args) -> None:
+    """L-BFGS iterations of the headline workload (energy + gradient per
+    evaluation, warm-started environments): energies and seconds per step."""
+    import torch
+    from paper_2502_10298_amd import inputs as inp
+    from paper_2502_10298_amd import optimize
+
+    w = inp.WORKLOADS[WORKLOAD]
+    A0 = torch.tensor(inp.workload_peps(WORKLOAD), device="cuda:0")
+    prec = args.prec or w["prec"]
+    t0 = time.perf_counter()
+    _, hist = optimize.lbfgs(A0, inp.workload_h(WORKLOAD), w["chi"], args.lbfgs, n_sweeps=args.grad_sweeps,
+                             ckpt_every=args.ckpt, prec=prec, pre_sweeps=args.pre_sweeps, alt_yr=args.alt_yr,
+                             half_teal=args.half_teal,
+                             on_eval=lambda r: say(f"L-BFGS evaluation: E = {r['energy']:.10f}, "
+                                                   f"{r['seconds']:.2f} s"))
+    total = time.perf_counter() - t0
+    iters = max(r["iteration"] for r in hist)
+    print(json.dumps({"lbfgs_iterations": iters, "evaluations": len(hist), "energies": [r["energy"] for r in hist],
+                      "seconds_per_evaluation": [r["seconds"] for r in hist],
+                      "seconds_per_iteration": sum(r["seconds"] for r in hist) / max(iters, 1),
+                      "total_seconds_with_start_environment": total, "dtype": prec,
+                      "config": {"workload": WORKLOAD, "sweeps_per_eval": args.grad_sweeps, "ckpt_every": args.ckpt,
+                                 "pre_sweeps": args.pre_sweeps, "projectors": projectors_label(args)}}), flush=True)
+
+
 def time_steps(obj, h, args, steps):
     """`steps` energy + gradient evaluations from the context's start
     environment; returns (E, dE/dA, seconds)."""
@@ -249,6 +278,9 @@ def main():
         sys.exit(1)
     if args.scaling:
         scaling(args)
+        return
+    if args.lbfgs:
+        lbfgs_run(args)
         return
     if args.copy_probe:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
