@@ -84,6 +84,21 @@ hipError_t svd_adj_prep(hipStream_t s, int nb, int chi, const double* U, const d
   return hipGetLastError();
 }
 
+__global__ void scale_cols_rsqrt_s_kernel(int nb, int chi, const double* X, const double* S, const int* kr,
+                                          double* out) {
+  const int k = kr[0];
+  long n = (long)nb * chi;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(i % chi);
+    out[i] = c < k ? X[i] / sqrt(S[c]) : 0.0;
+  }
+}
+hipError_t scale_cols_rsqrt_s(hipStream_t s, int nb, int chi, const double* X, const double* S, const int* kr,
+                              double* out) {
+  hipLaunchKernelGGL(scale_cols_rsqrt_s_kernel, dim3(gfor((long)nb * chi)), dim3(256), 0, s, nb, chi, X, S, kr, out);
+  return hipGetLastError();
+}
+
 __global__ void zero_rows_kernel(int nb, int chi, double* GU, double* GV, const int* r) {
   const int rr = *r;
   long n = (long)nb * chi;

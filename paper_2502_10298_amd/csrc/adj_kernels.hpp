@@ -14,6 +14,9 @@ hipError_t scale_cols_from(hipStream_t s, const void* src, bool src_f64, double*
 // Ubar = Xbar S^{-1/2}, Vbar = Ybar S^{-1/2}, Sbar = -1/2 S^{-3/2} diag(U^T Xbar + V^T Ybar) (first k columns)
 hipError_t svd_adj_prep(hipStream_t s, int nb, int chi, const double* U, const double* V, const double* S,
                         const int* kr, const double* Xb, const double* Yb, double* Ub, double* Vb, double* Sb);
+// out[i][c] = X[i][c] / sqrt(S[c]) for c < k (= kr[0]), zero otherwise (nb x chi)
+hipError_t scale_cols_rsqrt_s(hipStream_t s, int nb, int chi, const double* X, const double* S, const int* kr,
+                              double* out);
 // zero rows i >= *r of GU and GV (nb x chi)
 hipError_t zero_rows_from(hipStream_t s, int nb, int chi, double* GU, double* GV, const int* r);
 // inner matrix of the thin SVD adjoint, first c2 rows (Itop, c2 x nb) and the

@@ -783,11 +783,21 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_h
   Ten genv = E.alloc(E.cdt, {env_n});
   Ten gA = E.alloc(F64, {c->A64.n()});
   // SVD record / replay store: one slot per move of a checkpoint block, each
-  // bounded by the decompositions of every site of the cell (green, green',
-  // teal: n = chi_E D; yellow, yellow', red: n = chi_I p D)
+  // bounded by the decompositions of every site of the cell.  A matrix of
+  // size n decomposed in full keeps U, S, V (2 n^2 + n); one of size nb
+  // decomposed through its rank-r core keeps the core's U, S, V and the two
+  // Q^T factors (2 r^2 + r + 2 r nb).
   {
-    const long nE = (long)c->chiE * c->D, nI = (long)c->chiI * c->p * c->D;
-    const long per_site = 3 * (2 * nE * nE + nE) + 3 * (2 * nI * nI + nI);
+    const bool alt = (c->cfg.projector_variant & CTM_PROJ_ALT_YR) != 0;
+    const bool half = (c->cfg.projector_variant & CTM_PROJ_HALF_TEAL) != 0;
+    const long ce = c->chiE, ci = c->chiI, D = c->D, p = c->p;
+    auto full = [](long n) { return 2 * n * n + n; };
+    auto fact = [](long nb, long r) { return 2 * r * r + r + 2 * r * nb; };
+    const long green = full(ce * D);
+    const long teal = half ? fact(ce * D * D, ce * D) : full(ce * D);
+    const long yellow = alt ? full(ci * D) : fact(ci * p * D, ci * D);
+    const long red = alt ? full(ci * D) : std::max(full(ci * p * D), fact(ci * p * D, std::min(ce * D, ci * p * D)));
+    const long per_site = 2 * green + teal + 2 * yellow + red;
     const long per_slot = (long)c->Lx * c->Ly * per_site + 32L * 8 * (c->Lx + c->Ly) * 4;
     Ten buf = E.alloc(F64, {4L * ckpt, per_slot});
     E.svdc_setup(buf, 4 * ckpt, per_slot);

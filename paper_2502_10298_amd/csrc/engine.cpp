@@ -638,10 +638,10 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
   struct Group {
     std::vector<size_t> idx;
     long nb = 0, rk = 0, n = 0;   // n: size of the matrices handed to the Jacobi SVD
-    Ten Ub, Sb, Vb;               // n_b x n_b factors of M
+    Ten Ub, Sb, Vb;               // n x n factors of M (rk = 0) or of its core (rk > 0)
     bool replayed = false;
     long job0 = 0;                // first entry in the Jacobi batch of size n
-    Ten Xq, Rq, Qq;               // low-rank route: factors, R's and Q^T's
+    Ten Xq, Rq, Qq;               // low-rank route: factors, R's and Q^T's (Q_L^T then Q_R^T, rk x nb each)
   };
   std::vector<Group> groups;
   {
@@ -677,21 +677,27 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
       }
     }
   }
-  // replay of recorded decompositions (same group order as when recorded)
+  // replay of recorded decompositions (same group order as when recorded):
+  // U, S, V of size n, and for the low-rank route the Q^T factors
   for (Group& G : groups) {
-    const long nb = G.nb, g = (long)G.idx.size();
+    const long nb = G.nb, n = G.n, rk = G.rk, g = (long)G.idx.size();
     if (svdc_mode != 2 || svdc_slot < 0) continue;
     SvdCacheSlot& sl = svdc_slots[svdc_slot];
-    if (sl.valid && svdc_cursor < sl.off.size() && sl.nb[svdc_cursor] == nb && sl.g[svdc_cursor] == g) {
-      G.Ub = alloc(F64, {g, nb, nb});
-      G.Sb = alloc(F64, {g, nb});
-      G.Vb = alloc(F64, {g, nb, nb});
+    if (sl.valid && svdc_cursor < sl.off.size() && sl.nb[svdc_cursor] == nb && sl.g[svdc_cursor] == g &&
+        sl.rk[svdc_cursor] == rk) {
+      G.Ub = alloc(F64, {g, n, n});
+      G.Sb = alloc(F64, {g, n});
+      G.Vb = alloc(F64, {g, n, n});
+      if (rk) G.Qq = alloc(F64, {2 * g, rk, nb});
       if (!dry && ok()) {
         const double* src = svdc_buf.f64() + (long)svdc_slot * svdc_per_slot + sl.off[svdc_cursor];
-        const long un = g * nb * nb, sn = g * nb;
+        const long un = g * n * n, sn = g * n;
         check(hipMemcpyAsync(G.Ub.p, src, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
         check(hipMemcpyAsync(G.Sb.p, src + un, sizeof(double) * sn, hipMemcpyDeviceToDevice, s));
         check(hipMemcpyAsync(G.Vb.p, src + un + sn, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
+        if (rk)
+          check(hipMemcpyAsync(G.Qq.p, src + 2 * un + sn, sizeof(double) * 2 * g * rk * nb, hipMemcpyDeviceToDevice,
+                               s));
       }
       ++svdc_cursor;
       G.replayed = true;
@@ -716,16 +722,13 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
   }
   for (Group& G : groups) {
     if (G.replayed) continue;
-    const long nb = G.nb, g = (long)G.idx.size();
-    if (G.rk) {   // factors of M (n_b x n_b) beyond the core
-      G.Ub = alloc(F64, {g, nb, nb});
-      G.Sb = alloc(F64, {g, nb});
-      G.Vb = alloc(F64, {g, nb, nb});
-    } else {      // the Jacobi outputs are the factors themselves
-      G.Ub = view_of(*this, jU[G.n], G.job0 * nb * nb, {g, nb, nb});
-      G.Sb = view_of(*this, jS[G.n], G.job0 * nb, {g, nb});
-      G.Vb = view_of(*this, jV[G.n], G.job0 * nb * nb, {g, nb, nb});
-    }
+    const long n = G.n, g = (long)G.idx.size();
+    // the Jacobi outputs are the factors themselves (of the core on the
+    // low-rank route, whose Q^T factors are kept beside them)
+    G.Ub = view_of(*this, jU[n], G.job0 * n * n, {g, n, n});
+    G.Sb = view_of(*this, jS[n], G.job0 * n, {g, n});
+    G.Vb = view_of(*this, jV[n], G.job0 * n * n, {g, n, n});
+    if (G.rk) G.Qq = alloc(F64, {2 * g, G.rk, G.nb});
   }
   size_t mk = ar.mark();   // transient from here: Jacobi inputs, QR buffers, workspaces
   std::unordered_map<long, Ten> jM;
@@ -747,7 +750,6 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
     // M = L^T R with L, R: r0 x n_b  (entries 0..g-1: L, g..2g-1: R)
     G.Xq = alloc(F64, {2 * g, rk, nb});
     G.Rq = alloc(F64, {2 * g, rk, rk});
-    G.Qq = alloc(F64, {2 * g, rk, nb});
     for (long j = 0; j < g; ++j) {
       const ProjReq& q = reqs[G.idx[j]];
       const ProjSaved& P = ps[G.idx[j]];
@@ -822,39 +824,29 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
       }
     }
   }
-  // low-rank route: U = Q_L U', V = Q_R V' in the first r0 columns; the rest (and S beyond r0) are zero
-  for (Group& G : groups) {
-    if (G.replayed || !G.rk || dry || !ok()) continue;
-    const long nb = G.nb, rk = G.rk, g = (long)G.idx.size();
-    const long rr = rk * rk, rn = rk * nb, nn = nb * nb;
-    check(fill_f64(s, G.Ub.f64(), 0.0, g * nn));
-    check(fill_f64(s, G.Vb.f64(), 0.0, g * nn));
-    check(fill_f64(s, G.Sb.f64(), 0.0, g * nb));
-    check(gemm_f64(s, true, false, (int)nb, (int)rk, (int)rk, 1.0, G.Qq.f64(), nb, rn,
-                   jU[rk].f64() + G.job0 * rr, rk, rr, 0.0, G.Ub.f64(), nb, nn, (int)g));
-    check(gemm_f64(s, true, false, (int)nb, (int)rk, (int)rk, 1.0, G.Qq.f64() + g * rn, nb, rn,
-                   jV[rk].f64() + G.job0 * rr, rk, rr, 0.0, G.Vb.f64(), nb, nn, (int)g));
-    check(hipMemcpy2DAsync(G.Sb.p, sizeof(double) * nb, jS[rk].f64() + G.job0 * rk, sizeof(double) * rk,
-                           sizeof(double) * rk, g, hipMemcpyDeviceToDevice, s));
-  }
+  // low-rank route: M = Q_L (U' S V'^T) Q_R^T stays in that factored form (the
+  // QR wrote Q_L^T, Q_R^T into the persistent G.Qq); U = Q_L U', V = Q_R V' are
+  // formed only for the kept columns, below
   ar.release(mk);
   // record the decompositions of this call for a later replay
   for (Group& G : groups) {
     if (G.replayed || svdc_mode != 1 || svdc_slot < 0) continue;
-    const long nb = G.nb, g = (long)G.idx.size();
+    const long nb = G.nb, n = G.n, rk = G.rk, g = (long)G.idx.size();
     SvdCacheSlot& sl = svdc_slots[svdc_slot];
-    const long un = g * nb * nb, sn = g * nb;
-    const long need = ((2 * un + sn + 31) / 32) * 32;
+    const long un = g * n * n, sn = g * n, qn = rk ? 2 * g * rk * nb : 0;
+    const long need = ((2 * un + sn + qn + 31) / 32) * 32;
     if (sl.valid && sl.used + need <= sl.cap) {
       if (!dry && ok()) {
         double* dst = svdc_buf.f64() + (long)svdc_slot * svdc_per_slot + sl.used;
         check(hipMemcpyAsync(dst, G.Ub.p, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
         check(hipMemcpyAsync(dst + un, G.Sb.p, sizeof(double) * sn, hipMemcpyDeviceToDevice, s));
         check(hipMemcpyAsync(dst + un + sn, G.Vb.p, sizeof(double) * un, hipMemcpyDeviceToDevice, s));
+        if (rk) check(hipMemcpyAsync(dst + 2 * un + sn, G.Qq.p, sizeof(double) * qn, hipMemcpyDeviceToDevice, s));
       }
       sl.off.push_back(sl.used);
       sl.nb.push_back(nb);
       sl.g.push_back(g);
+      sl.rk.push_back(rk);
       sl.used += need;
     } else {
       sl.valid = false;   // a later replay of this move recomputes everything
@@ -862,24 +854,43 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
   }
   // projector formation
   for (Group& G : groups) {
-    const long nb = G.nb;
+    const long nb = G.nb, n = G.n, rk = G.rk, g = (long)G.idx.size();
     for (size_t j = 0; j < G.idx.size(); ++j) {
       const size_t i = G.idx[j];
       const ProjReq& q = reqs[i];
       ProjSaved& P = ps[i];
       const long na = P.na;
       const int chi = q.chi;
-      P.U = view_of(*this, G.Ub, (long)j * nb * nb, {nb, nb});
-      P.S = view_of(*this, G.Sb, (long)j * nb, {nb});
-      P.V = view_of(*this, G.Vb, (long)j * nb * nb, {nb, nb});
+      P.rk = (int)rk;
+      P.U = view_of(*this, G.Ub, (long)j * n * n, {n, n});
+      P.S = view_of(*this, G.Sb, (long)j * n, {n});
+      P.V = view_of(*this, G.Vb, (long)j * n * n, {n, n});
+      if (rk) {
+        P.QLt = view_of(*this, G.Qq, (long)j * rk * nb, {rk, nb});
+        P.QRt = view_of(*this, G.Qq, (long)(g + j) * rk * nb, {rk, nb});
+      }
       P.kr = alloc(F64, {2});   // two ints (k, r) in its first 8 bytes
       P.X = alloc(F64, {nb, chi});
       P.Y = alloc(F64, {nb, chi});
       if (!dry && ok()) {
         int* kr = (int*)P.kr.p;
-        check(trunc_scale(s, (int)nb, (int)nb, chi, P.U.f64(), P.S.f64(), cutoff, P.X.f64(), kr, 1));
-        check(trunc_scale(s, (int)nb, (int)nb, chi, P.V.f64(), P.S.f64(), cutoff, P.Y.f64(), kr, 1));
-        check(rank_count(s, (int)nb, P.S.f64(), 1e-14, kr + 1));
+        if (!rk) {
+          check(trunc_scale(s, (int)nb, (int)nb, chi, P.U.f64(), P.S.f64(), cutoff, P.X.f64(), kr, 1));
+          check(trunc_scale(s, (int)nb, (int)nb, chi, P.V.f64(), P.S.f64(), cutoff, P.Y.f64(), kr, 1));
+        }
+        check(rank_count(s, (int)n, P.S.f64(), 1e-14, kr + 1));
+      }
+      if (rk) {   // X = Q_L (U'_k S_k^{-1/2}), Y = Q_R (V'_k S_k^{-1/2}): the kept columns only
+        size_t m3 = ar.mark();
+        Ten Xc = alloc(F64, {rk, chi}), Yc = alloc(F64, {rk, chi});
+        if (!dry && ok()) {
+          int* kr = (int*)P.kr.p;
+          check(trunc_scale(s, (int)rk, (int)rk, chi, P.U.f64(), P.S.f64(), cutoff, Xc.f64(), kr, 1));
+          check(trunc_scale(s, (int)rk, (int)rk, chi, P.V.f64(), P.S.f64(), cutoff, Yc.f64(), kr, 1));
+        }
+        gemm(true, false, (int)nb, chi, (int)rk, 1.0, P.QLt, 0, nb, Xc, 0, chi, 0.0, P.X, 0, chi);
+        gemm(true, false, (int)nb, chi, (int)rk, 1.0, P.QRt, 0, nb, Yc, 0, chi, 0.0, P.Y, 0, chi);
+        ar.release(m3);
       }
       Ten PT64 = alloc(F64, {na, chi}), PB64 = alloc(F64, {na, chi});
       if (q.rows) {   // P_T = rho_B X, P_B = rho_T Y
@@ -891,9 +902,9 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
       }
       P.sgn = alloc(F64, {chi});
       if (!dry && ok()) check(sign_fix(s, (int)na, chi, PT64.f64(), PB64.f64(), P.sgn.f64(), 1));
-      if (q.spectrum_out && !dry && ok()) {
-        q.spectrum_out->resize(nb);
-        check(hipMemcpyAsync(q.spectrum_out->data(), P.S.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+      if (q.spectrum_out && !dry && ok()) {   // the nonzero part of M's spectrum (length n)
+        q.spectrum_out->resize(n);
+        check(hipMemcpyAsync(q.spectrum_out->data(), P.S.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         check(hipStreamSynchronize(s));
       }
       std::vector<long> pshape = a_shapes[i];
@@ -1021,8 +1032,11 @@ void Engine::backward() {
 //   G_U = U_r^T Ubar, G_V = V_r^T Vbar; then rho_Bbar += rho_T Mbar^T,
 //   rho_Tbar += rho_B Mbar (rows case; the columns case is transposed).
 // Ubar and Vbar have only chi nonzero columns, so every product is
-// O(b^2 chi) except none: the inner matrix is split into its first chi rows
-// and first chi columns.
+// O(b^2 chi): the inner matrix is split into its first chi rows and first chi
+// columns.  On the low-rank route (M = Q_L K Q_R^T, K = U' S V'^T of size
+// rk) the same formula runs in the core's basis with U = Q_L U', V = Q_R V'
+// and the complement term taken in the full space, so every product is
+// O(b rk chi) and no b x b factor is ever formed.
 void Engine::proj_backward(TapeRec& r) {
   ProjSaved& ps = r.proj;
   const int na = ps.na, nb = ps.nb, chi = ps.chi;
@@ -1049,64 +1063,132 @@ void Engine::proj_backward(TapeRec& r) {
     gemm(false, true, nb, na, chi, 1.0, ps.Y, 0, chi, PBb, 0, chi, 1.0, rTb, 0, na);
     gemm(false, false, nb, chi, na, 1.0, ps.rT, 0, na, PBb, 0, chi, 0.0, Yb, 0, chi);
   }
-  // Ubar, Vbar, Sbar
-  Ten Ub = alloc(F64, {nb, chi}), Vb = alloc(F64, {nb, chi}), Sb = alloc(F64, {chi});
-  if (!dry && ok())
-    check(svd_adj_prep(s, nb, chi, ps.U.f64(), ps.V.f64(), ps.S.f64(), (const int*)ps.kr.p, Xb.f64(), Yb.f64(),
-                       Ub.f64(), Vb.f64(), Sb.f64()));
-  // G_U = U^T Ubar, G_V = V^T Vbar (b x chi), rows >= r zeroed
-  Ten GU = alloc(F64, {nb, chi}), GV = alloc(F64, {nb, chi});
-  gemm(true, false, nb, chi, nb, 1.0, ps.U, 0, nb, Ub, 0, chi, 0.0, GU, 0, chi);
-  gemm(true, false, nb, chi, nb, 1.0, ps.V, 0, nb, Vb, 0, chi, 0.0, GV, 0, chi);
-  if (!dry && ok()) check(zero_rows_from(s, nb, chi, GU.f64(), GV.f64(), (const int*)ps.kr.p + 1));
-  // inner blocks: top = inner[0:chi, :] (chi x b), left = inner[chi:, 0:chi] ((b-chi) x chi)
-  const int c2 = std::min(chi, nb);
-  Ten Itop = alloc(F64, {c2, nb});
-  Ten Ileft = alloc(F64, {std::max(nb - c2, 1), c2});
-  if (!dry && ok())
-    check(svd_adj_inner(s, nb, c2, chi, ps.S.f64(), Sb.f64(), GU.f64(), GV.f64(), (const int*)ps.kr.p, adj_eps,
-                        Itop.f64(), Ileft.f64()));
-  // C1 = (Ubar - U G_U) S^{-1}, C2 = (Vbar - V G_V) S^{-1}   (b x chi)
-  Ten C1 = alloc(F64, {nb, chi}), C2 = alloc(F64, {nb, chi});
-  if (!dry && ok()) {
-    check(hipMemcpyAsync(C1.p, Ub.p, Ub.bytes(), hipMemcpyDeviceToDevice, s));
-    check(hipMemcpyAsync(C2.p, Vb.p, Vb.bytes(), hipMemcpyDeviceToDevice, s));
+  // Mbar in the factored form U_c Q1 + Q2 V_c^T (U_c, V_c: n_b x c2, the first
+  // c2 singular vectors, at leading dimension ldu, ldv)
+  Ten Q1, Q2, Ucm, Vcm;
+  long ldu = nb, ldv = nb;
+  int c2 = std::min(chi, nb);
+  if (!ps.rk) {
+    // Ubar, Vbar, Sbar
+    Ten Ub = alloc(F64, {nb, chi}), Vb = alloc(F64, {nb, chi}), Sb = alloc(F64, {chi});
+    if (!dry && ok())
+      check(svd_adj_prep(s, nb, chi, ps.U.f64(), ps.V.f64(), ps.S.f64(), (const int*)ps.kr.p, Xb.f64(), Yb.f64(),
+                         Ub.f64(), Vb.f64(), Sb.f64()));
+    // G_U = U^T Ubar, G_V = V^T Vbar (b x chi), rows >= r zeroed
+    Ten GU = alloc(F64, {nb, chi}), GV = alloc(F64, {nb, chi});
+    gemm(true, false, nb, chi, nb, 1.0, ps.U, 0, nb, Ub, 0, chi, 0.0, GU, 0, chi);
+    gemm(true, false, nb, chi, nb, 1.0, ps.V, 0, nb, Vb, 0, chi, 0.0, GV, 0, chi);
+    if (!dry && ok()) check(zero_rows_from(s, nb, chi, GU.f64(), GV.f64(), (const int*)ps.kr.p + 1));
+    // inner blocks: top = inner[0:chi, :] (chi x b), left = inner[chi:, 0:chi] ((b-chi) x chi)
+    Ten Itop = alloc(F64, {c2, nb});
+    Ten Ileft = alloc(F64, {std::max(nb - c2, 1), c2});
+    if (!dry && ok())
+      check(svd_adj_inner(s, nb, c2, chi, ps.S.f64(), Sb.f64(), GU.f64(), GV.f64(), (const int*)ps.kr.p, adj_eps,
+                          Itop.f64(), Ileft.f64()));
+    // C1 = (Ubar - U G_U) S^{-1}, C2 = (Vbar - V G_V) S^{-1}   (b x chi)
+    Ten C1 = alloc(F64, {nb, chi}), C2 = alloc(F64, {nb, chi});
+    if (!dry && ok()) {
+      check(hipMemcpyAsync(C1.p, Ub.p, Ub.bytes(), hipMemcpyDeviceToDevice, s));
+      check(hipMemcpyAsync(C2.p, Vb.p, Vb.bytes(), hipMemcpyDeviceToDevice, s));
+    }
+    gemm(false, false, nb, chi, nb, -1.0, ps.U, 0, nb, GU, 0, chi, 1.0, C1, 0, chi);
+    gemm(false, false, nb, chi, nb, -1.0, ps.V, 0, nb, GV, 0, chi, 1.0, C2, 0, chi);
+    if (!dry && ok()) check(scale_cols_inv_s(s, nb, chi, C1.f64(), C2.f64(), ps.S.f64(), (const int*)ps.kr.p));
+    // Q1 = Itop V^T + C2^T  (c2 x b);  Q2 = U[:, c2:] Ileft + C1[:, :c2]  (b x c2)
+    Q1 = alloc(F64, {c2, nb});
+    Q2 = alloc(F64, {nb, c2});
+    gemm(false, true, c2, nb, nb, 1.0, Itop, 0, nb, ps.V, 0, nb, 0.0, Q1, 0, nb);
+    if (!dry && ok()) check(add_transposed(s, nb, chi, c2, C2.f64(), Q1.f64()));   // Q1[c][b] += C2[b][c]
+    if (!dry && ok()) check(copy_cols(s, nb, chi, c2, C1.f64(), Q2.f64()));         // Q2 = C1[:, :c2]
+    if (nb > c2) gemm(false, false, nb, c2, nb - c2, 1.0, ps.U, c2, nb, Ileft, 0, c2, 1.0, Q2, 0, c2);
+    Ucm = ps.U;
+    Vcm = ps.V;
+  } else {
+    // M = Q_L K Q_R^T with the core K = U' S V'^T (rk x rk) and Q_L^T Q_L =
+    // Q_R^T Q_R = 1: U = Q_L U' and V = Q_R V' span the column and row spaces
+    // of M, and the same adjoint runs in the core's basis.  Ubar splits into
+    // its part in span(Q_L), Q_L (Q_L^T Ubar), and the rest, which enters
+    // through the complement term (Ubar - U U^T Ubar) S^{-1} only.
+    const int rk = ps.rk;
+    c2 = std::min(chi, rk);
+    Ten Xc = alloc(F64, {rk, chi}), Yc = alloc(F64, {rk, chi});
+    gemm(false, false, rk, chi, nb, 1.0, ps.QLt, 0, nb, Xb, 0, chi, 0.0, Xc, 0, chi);   // Q_L^T Xbar
+    gemm(false, false, rk, chi, nb, 1.0, ps.QRt, 0, nb, Yb, 0, chi, 0.0, Yc, 0, chi);   // Q_R^T Ybar
+    Ten Ubc = alloc(F64, {rk, chi}), Vbc = alloc(F64, {rk, chi}), Sb = alloc(F64, {chi});
+    Ten Ub = alloc(F64, {nb, chi}), Vb = alloc(F64, {nb, chi});
+    if (!dry && ok()) {
+      // core: Ubar' = Q_L^T Ubar and Sbar (u_c . xbar_c = u'_c . (Q_L^T xbar)_c)
+      check(svd_adj_prep(s, rk, chi, ps.U.f64(), ps.V.f64(), ps.S.f64(), (const int*)ps.kr.p, Xc.f64(), Yc.f64(),
+                         Ubc.f64(), Vbc.f64(), Sb.f64()));
+      // full space: Ubar = Xbar S^{-1/2}, Vbar = Ybar S^{-1/2}
+      check(scale_cols_rsqrt_s(s, nb, chi, Xb.f64(), ps.S.f64(), (const int*)ps.kr.p, Ub.f64()));
+      check(scale_cols_rsqrt_s(s, nb, chi, Yb.f64(), ps.S.f64(), (const int*)ps.kr.p, Vb.f64()));
+    }
+    // G_U = U'^T Ubar' = U^T Ubar, G_V likewise (rk x chi), rows >= r zeroed
+    Ten GU = alloc(F64, {rk, chi}), GV = alloc(F64, {rk, chi});
+    gemm(true, false, rk, chi, rk, 1.0, ps.U, 0, rk, Ubc, 0, chi, 0.0, GU, 0, chi);
+    gemm(true, false, rk, chi, rk, 1.0, ps.V, 0, rk, Vbc, 0, chi, 0.0, GV, 0, chi);
+    if (!dry && ok()) check(zero_rows_from(s, rk, chi, GU.f64(), GV.f64(), (const int*)ps.kr.p + 1));
+    // inner blocks in the core's basis (the inner matrix vanishes beyond rk)
+    Ten Itop = alloc(F64, {c2, rk});
+    Ten Ileft = alloc(F64, {std::max(rk - c2, 1), c2});
+    if (!dry && ok())
+      check(svd_adj_inner(s, rk, c2, chi, ps.S.f64(), Sb.f64(), GU.f64(), GV.f64(), (const int*)ps.kr.p, adj_eps,
+                          Itop.f64(), Ileft.f64()));
+    // C1 = (Ubar - Q_L (U' G_U)) S^{-1}, C2 = (Vbar - Q_R (V' G_V)) S^{-1}  (nb x chi, in place)
+    Ten T1 = alloc(F64, {rk, chi}), T2 = alloc(F64, {rk, chi});
+    gemm(false, false, rk, chi, rk, 1.0, ps.U, 0, rk, GU, 0, chi, 0.0, T1, 0, chi);
+    gemm(false, false, rk, chi, rk, 1.0, ps.V, 0, rk, GV, 0, chi, 0.0, T2, 0, chi);
+    Ten C1 = Ub, C2 = Vb;
+    gemm(true, false, nb, chi, rk, -1.0, ps.QLt, 0, nb, T1, 0, chi, 1.0, C1, 0, chi);
+    gemm(true, false, nb, chi, rk, -1.0, ps.QRt, 0, nb, T2, 0, chi, 1.0, C2, 0, chi);
+    if (!dry && ok()) check(scale_cols_inv_s(s, nb, chi, C1.f64(), C2.f64(), ps.S.f64(), (const int*)ps.kr.p));
+    // U_c = Q_L U'[:, :c2], V_c = Q_R V'[:, :c2]  (nb x c2)
+    Ucm = alloc(F64, {nb, c2});
+    Vcm = alloc(F64, {nb, c2});
+    gemm(true, false, nb, c2, rk, 1.0, ps.QLt, 0, nb, ps.U, 0, rk, 0.0, Ucm, 0, c2);
+    gemm(true, false, nb, c2, rk, 1.0, ps.QRt, 0, nb, ps.V, 0, rk, 0.0, Vcm, 0, c2);
+    ldu = ldv = c2;
+    // Q1 = (Itop V'^T) Q_R^T + C2^T  (c2 x nb)
+    Ten T3 = alloc(F64, {c2, rk});
+    gemm(false, true, c2, rk, rk, 1.0, Itop, 0, rk, ps.V, 0, rk, 0.0, T3, 0, rk);
+    Q1 = alloc(F64, {c2, nb});
+    gemm(false, false, c2, nb, rk, 1.0, T3, 0, rk, ps.QRt, 0, nb, 0.0, Q1, 0, nb);
+    if (!dry && ok()) check(add_transposed(s, nb, chi, c2, C2.f64(), Q1.f64()));
+    // Q2 = Q_L (U'[:, c2:] Ileft) + C1[:, :c2]  (nb x c2)
+    Q2 = alloc(F64, {nb, c2});
+    if (!dry && ok()) check(copy_cols(s, nb, chi, c2, C1.f64(), Q2.f64()));
+    if (rk > c2) {
+      Ten T4 = alloc(F64, {rk, c2});
+      gemm(false, false, rk, c2, rk - c2, 1.0, ps.U, c2, rk, Ileft, 0, c2, 0.0, T4, 0, c2);
+      gemm(true, false, nb, c2, rk, 1.0, ps.QLt, 0, nb, T4, 0, c2, 1.0, Q2, 0, c2);
+    }
   }
-  gemm(false, false, nb, chi, nb, -1.0, ps.U, 0, nb, GU, 0, chi, 1.0, C1, 0, chi);
-  gemm(false, false, nb, chi, nb, -1.0, ps.V, 0, nb, GV, 0, chi, 1.0, C2, 0, chi);
-  if (!dry && ok()) check(scale_cols_inv_s(s, nb, chi, C1.f64(), C2.f64(), ps.S.f64(), (const int*)ps.kr.p));
-  // Q1 = Itop V^T + C2^T  (c2 x b);  Q2 = U[:, c2:] Ileft + C1[:, :c2]  (b x c2)
-  Ten Q1 = alloc(F64, {c2, nb}), Q2 = alloc(F64, {nb, c2});
-  gemm(false, true, c2, nb, nb, 1.0, Itop, 0, nb, ps.V, 0, nb, 0.0, Q1, 0, nb);
-  if (!dry && ok()) check(add_transposed(s, nb, chi, c2, C2.f64(), Q1.f64()));   // Q1[c][b] += C2[b][c]
-  if (!dry && ok()) check(copy_cols(s, nb, chi, c2, C1.f64(), Q2.f64()));         // Q2 = C1[:, :c2]
-  if (nb > c2) gemm(false, false, nb, c2, nb - c2, 1.0, ps.U, c2, nb, Ileft, 0, c2, 1.0, Q2, 0, c2);
-  // Mbar = U_c Q1 + Q2 V_c^T (U_c, V_c: the first c2 columns) has rank <= 2 c2;
-  // the rho bars take it in this factored form (never the b x b matrix):
-  // O(na b c2) instead of O(na b^2)
+  // Mbar = U_c Q1 + Q2 V_c^T has rank <= 2 c2; the rho bars take it in this
+  // factored form (never the b x b matrix): O(na b c2) instead of O(na b^2)
   Ten A1 = alloc(F64, {na, c2}), A2 = alloc(F64, {na, c2});
   if (rows) {   // M = rB^T rT  (rho: na x nb)
     // rBb += rT Mb^T = (rT Q1^T) U_c^T + (rT V_c) Q2^T
     gemm(false, true, na, c2, nb, 1.0, ps.rT, 0, nb, Q1, 0, nb, 0.0, A1, 0, c2);
-    gemm(false, false, na, c2, nb, 1.0, ps.rT, 0, nb, ps.V, 0, nb, 0.0, A2, 0, c2);
-    gemm(false, true, na, nb, c2, 1.0, A1, 0, c2, ps.U, 0, nb, 1.0, rBb, 0, nb);
+    gemm(false, false, na, c2, nb, 1.0, ps.rT, 0, nb, Vcm, 0, ldv, 0.0, A2, 0, c2);
+    gemm(false, true, na, nb, c2, 1.0, A1, 0, c2, Ucm, 0, ldu, 1.0, rBb, 0, nb);
     gemm(false, true, na, nb, c2, 1.0, A2, 0, c2, Q2, 0, c2, 1.0, rBb, 0, nb);
     // rTb += rB Mb = (rB U_c) Q1 + (rB Q2) V_c^T
-    gemm(false, false, na, c2, nb, 1.0, ps.rB, 0, nb, ps.U, 0, nb, 0.0, A1, 0, c2);
+    gemm(false, false, na, c2, nb, 1.0, ps.rB, 0, nb, Ucm, 0, ldu, 0.0, A1, 0, c2);
     gemm(false, false, na, c2, nb, 1.0, ps.rB, 0, nb, Q2, 0, c2, 0.0, A2, 0, c2);
     gemm(false, false, na, nb, c2, 1.0, A1, 0, c2, Q1, 0, nb, 1.0, rTb, 0, nb);
-    gemm(false, true, na, nb, c2, 1.0, A2, 0, c2, ps.V, 0, nb, 1.0, rTb, 0, nb);
+    gemm(false, true, na, nb, c2, 1.0, A2, 0, c2, Vcm, 0, ldv, 1.0, rTb, 0, nb);
   } else {      // M = rB rT^T  (rho: nb x na); A1, A2 hold c2 x na products here
     // rBb += Mb rT = U_c (Q1 rT) + Q2 (V_c^T rT)
     gemm(false, false, c2, na, nb, 1.0, Q1, 0, nb, ps.rT, 0, na, 0.0, A1, 0, na);
-    gemm(true, false, c2, na, nb, 1.0, ps.V, 0, nb, ps.rT, 0, na, 0.0, A2, 0, na);
-    gemm(false, false, nb, na, c2, 1.0, ps.U, 0, nb, A1, 0, na, 1.0, rBb, 0, na);
+    gemm(true, false, c2, na, nb, 1.0, Vcm, 0, ldv, ps.rT, 0, na, 0.0, A2, 0, na);
+    gemm(false, false, nb, na, c2, 1.0, Ucm, 0, ldu, A1, 0, na, 1.0, rBb, 0, na);
     gemm(false, false, nb, na, c2, 1.0, Q2, 0, c2, A2, 0, na, 1.0, rBb, 0, na);
     // rTb += Mb^T rB = Q1^T (U_c^T rB) + V_c (Q2^T rB)
-    gemm(true, false, c2, na, nb, 1.0, ps.U, 0, nb, ps.rB, 0, na, 0.0, A1, 0, na);
+    gemm(true, false, c2, na, nb, 1.0, Ucm, 0, ldu, ps.rB, 0, na, 0.0, A1, 0, na);
     gemm(true, false, c2, na, nb, 1.0, Q2, 0, c2, ps.rB, 0, na, 0.0, A2, 0, na);
     gemm(true, false, nb, na, c2, 1.0, Q1, 0, nb, A1, 0, na, 1.0, rTb, 0, na);
-    gemm(false, false, nb, na, c2, 1.0, ps.V, 0, nb, A2, 0, na, 1.0, rTb, 0, na);
+    gemm(false, false, nb, na, c2, 1.0, Vcm, 0, ldv, A2, 0, na, 1.0, rTb, 0, na);
   }
   Ten gT = grad(r.in[0]);
   Ten gB = grad(r.in[1]);

@@ -62,10 +62,12 @@ enum OpKind : int { OP_CONTRACT, OP_PERMUTE, OP_COPY, OP_CAST, OP_NORMALIZE, OP_
 
 struct ProjSaved {
   Ten rT, rB;          // FP64 copies of the half networks (na x nb)
-  Ten U, S, V, X, Y;   // SVD of M and the scaled truncated factors
+  Ten U, S, V, X, Y;   // SVD of M (or of its core, rk > 0) and the scaled truncated factors (nb x chi)
+  Ten QLt, QRt;        // rk > 0: M = Q_L (U S V^T) Q_R^T with Q_L^T, Q_R^T (rk x nb) orthonormal rows
   Ten sgn;             // sign of every projector column
   Ten kr;              // device ints: [k, r]
   int na = 0, nb = 0, chi = 0;
+  int rk = 0;          // > 0: M has rank <= rk and U, S, V are those of the rk x rk core
   bool rows = true;    // truncated legs are the rows of rho (else the columns)
 };
 
@@ -159,7 +161,7 @@ struct Engine {
   struct SvdCacheSlot {
     long cap = 0, used = 0;
     bool valid = false;
-    std::vector<long> off, nb, g;
+    std::vector<long> off, nb, g, rk;
   };
   Ten svdc_buf;                      // FP64, nslots * per_slot elements
   long svdc_per_slot = 0;
@@ -186,6 +188,7 @@ struct Engine {
       sl.off.clear();
       sl.nb.clear();
       sl.g.clear();
+      sl.rk.clear();
     }
   }
   void svdc_reset() {
