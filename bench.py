@@ -3,7 +3,8 @@
 One step = one energy + gradient evaluation at the headline workload (2x2
 unit cell of four distinct real tensors, p = 2, D = 8, chi_E = chi_I = 128,
 BF16x3 contractions with FP32 accumulation, FP64 projectors): `--grad-sweeps`
-split-CTMRG sweeps from the current (pre-converged) environment with
+split-CTMRG sweeps from a start environment (`--pre-sweeps` sweeps from the
+identity boundary, the same for every timed step) with
 checkpoints every `--ckpt` sweeps, the nearest-neighbour Heisenberg energy,
 and dE/dA by the hand-written reverse pass.  Forward-only sweeps/s is timed
 separately on the same context.  Inputs are seeded synthetic tensors already
@@ -12,8 +13,8 @@ resident in HBM.
 Prints one JSON line (see the keys below); `roofline` is taken from the
 library's own HIP-event timing of the dominant kernel class over the timed
 steps (events on every `--timing-stride`-th launch of each class, so that the
-events' host cost stays out of the timed run), `cpu_baseline` from the FP64 CPU oracle on a bounded sample (one
-column of one left move at the same sizes).
+events' host cost stays out of the timed run), `cpu_baseline` from the FP64 CPU oracle on a bounded sample (one column of
+one left move at the same sizes, forward and reverse).
 """
 from __future__ import annotations
 
@@ -127,10 +128,14 @@ def measured_traffic(kernel: str):
         return None
 
 
-def cpu_baseline(threads: int) -> dict:
-    """The FP64 oracle on one column of one left move (projectors of every
-    colour and the new C1, T4k, T4b, C4 of both rows) at D = 8, chi = 128,
-    scaled to sweeps/s: a 2x2-cell sweep is 4 moves x 2 columns."""
+def cpu_baseline(threads: int, n_sweeps: int) -> dict:
+    """The FP64 oracle on one column of one left move at D = 8, chi = 128:
+    the forward pass (projectors of every colour, the new C1, T4k, T4b, C4 of
+    both rows) and its reverse pass by autograd from a seeded cotangent on the
+    new tensors.  Scaled to energy-gradient evaluations per second: an
+    evaluation is n_sweeps sweeps of 4 moves x Ly columns, forward and reverse
+    (the energy term and its reverse pass are left out, which flatters the
+    CPU)."""
     import torch
     from oracle import split_ctmrg as sc
     from paper_2502_10298_amd import inputs as inp
@@ -141,13 +146,26 @@ def cpu_baseline(threads: int) -> dict:
     w = inp.WORKLOADS[WORKLOAD]
     env = sc.env_from_numpy(inp.random_env(7, w["Lx"], w["Ly"], w["D"], w["chi"], w["chi"]))
     A = sc.peps_from_numpy(inp.workload_peps(WORKLOAD))
+    for e in env.values():
+        for k in list(e):
+            e[k] = e[k].detach().requires_grad_(True)
+    for k in A:
+        A[k] = A[k].detach().requires_grad_(True)
     t0 = time.perf_counter()
     sc.left_move_column(env, A, w["Lx"], w["Ly"], 0, w["chi"], w["chi"])
-    dt = time.perf_counter() - t0
-    per_sweep = dt * 4 * w["Ly"]
-    return {"value": 1.0 / per_sweep, "unit": "sweeps/s", "cores": used, "kind": "oracle",
-            "sample": f"one column of one left move (2 site-moves) at 2x2, D=8, chi=128, FP64, "
-                      f"{dt:.1f} s, scaled x{4 * w['Ly']} to one sweep"}
+    t1 = time.perf_counter()
+    gen = torch.Generator().manual_seed(3)
+    new = [t for e in env.values() for t in e.values() if t.grad_fn is not None]
+    loss = sum((t * torch.randn(t.shape, generator=gen, dtype=t.dtype)).sum() for t in new)
+    t2 = time.perf_counter()
+    loss.backward()
+    t3 = time.perf_counter()
+    dt = (t1 - t0) + (t3 - t2)
+    scale = n_sweeps * 4 * w["Ly"]
+    return {"value": 1.0 / (dt * scale), "unit": "energy-grad evals/s", "cores": used, "kind": "oracle",
+            "sample": f"one column of one left move (2 site-moves) at 2x2, D=8, chi=128, FP64, forward "
+                      f"{t1 - t0:.1f} s + reverse {t3 - t2:.1f} s, scaled x{scale} to one evaluation of "
+                      f"{n_sweeps} sweeps (energy term not counted)"}
 
 
 def projectors_label(args) -> str:
@@ -369,7 +387,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         say("CPU oracle sample")
-        cpu = cpu_baseline(args.cpu_threads)
+        cpu = cpu_baseline(args.cpu_threads, args.grad_sweeps)
 
     out = {
         "metric": METRIC,

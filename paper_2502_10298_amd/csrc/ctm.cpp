@@ -577,6 +577,28 @@ void energies(ctm_ctx& c, const Env& env, const Peps& A, std::vector<Ten>& eh, s
     for (int y = 0; y < c.Ly; ++y) eh[(size_t)x * c.Ly + y] = E.bond_energy(vertical_rho(E, te, ta, y, x), c.h64, c.p);
 }
 
+// Energy per site on the device: the bond energies (value slot of each
+// [value, norm] pair) are gathered into one buffer, averaged over the sites by
+// site_energy, and returned to the host with one copy.  bonds (optional, host,
+// 2 Lx Ly entries) receives e_h, e_v of each site in site order.
+double site_energy_dev(ctm_ctx& c, const std::vector<Ten>& eh, const std::vector<Ten>& ev, double* bonds) {
+  Engine& E = c.E;
+  const int nb = (int)(eh.size() + ev.size());
+  Ten buf = E.alloc(F64, {(long)nb + 1});
+  std::vector<double> hv((size_t)nb + 1, 0.0);
+  if (!E.dry && E.ok()) {
+    for (size_t i = 0; i < eh.size(); ++i) {
+      E.check(hipMemcpyAsync(buf.f64() + 2 * i, eh[i].p, sizeof(double), hipMemcpyDeviceToDevice, E.s));
+      E.check(hipMemcpyAsync(buf.f64() + 2 * i + 1, ev[i].p, sizeof(double), hipMemcpyDeviceToDevice, E.s));
+    }
+    E.check(site_energy(E.s, nb, buf.f64(), 1.0 / ((double)c.Lx * c.Ly), buf.f64() + nb));
+    E.check(hipMemcpyAsync(hv.data(), buf.p, hv.size() * sizeof(double), hipMemcpyDeviceToHost, E.s));
+    E.check(hipStreamSynchronize(E.s));
+  }
+  if (bonds) std::copy(hv.begin(), hv.begin() + nb, bonds);
+  return hv[nb];
+}
+
 int status_from_engine(const Engine& E) {
   if (E.err != hipSuccess) return CTM_EDEVICE;
   if (E.ar.overflow) return CTM_EINVAL;
@@ -859,16 +881,8 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_h
     energies(*c, env, Ai, eh, ev);
     E.taping = false;
     const double w = 1.0 / (c->Lx * c->Ly);
-    std::vector<double> hv((size_t)c->Lx * c->Ly * 4, 0.0);
-    if (!E.dry && E.ok()) {
-      for (size_t i = 0; i < eh.size(); ++i) {
-        E.check(hipMemcpyAsync(&hv[4 * i], eh[i].p, 2 * sizeof(double), hipMemcpyDeviceToHost, E.s));
-        E.check(hipMemcpyAsync(&hv[4 * i + 2], ev[i].p, 2 * sizeof(double), hipMemcpyDeviceToHost, E.s));
-      }
-      E.check(hipStreamSynchronize(E.s));
-    }
+    esum = site_energy_dev(*c, eh, ev, nullptr);
     for (size_t i = 0; i < eh.size(); ++i) {
-      esum += w * (hv[4 * i] + hv[4 * i + 2]);
       Ten g1 = E.grad(eh[i]), g2 = E.grad(ev[i]);
       if (!E.dry && E.ok()) {
         E.check(fill_f64(E.s, g1.f64(), w, 1));
@@ -1162,23 +1176,7 @@ ctm_status ctm_energy_hv(ctm_ctx* c, const double* h_host, const double* hv_host
   Env env = view_env(*c, c->cur_blk);
   std::vector<Ten> eh, ev;
   energies(*c, env, A, eh, ev);
-  std::vector<double> hv(eh.size() * 4, 0.0);
-  if (E.ok()) {
-    for (size_t i = 0; i < eh.size(); ++i) {
-      E.check(hipMemcpyAsync(&hv[4 * i], eh[i].p, 2 * sizeof(double), hipMemcpyDeviceToHost, E.s));
-      E.check(hipMemcpyAsync(&hv[4 * i + 2], ev[i].p, 2 * sizeof(double), hipMemcpyDeviceToHost, E.s));
-    }
-    E.check(hipStreamSynchronize(E.s));
-  }
-  double tot = 0.0;
-  for (size_t i = 0; i < eh.size(); ++i) {
-    tot += hv[4 * i] + hv[4 * i + 2];
-    if (e_bonds) {
-      e_bonds[2 * i] = hv[4 * i];
-      e_bonds[2 * i + 1] = hv[4 * i + 2];
-    }
-  }
-  tot /= (double)eh.size();
+  const double tot = site_energy_dev(*c, eh, ev, e_bonds);
   if (e_site) *e_site = tot;
   ctm_status st = (ctm_status)status_from_engine(E);
   if (st == CTM_OK && !std::isfinite(tot)) st = CTM_ENUMERIC;

@@ -118,5 +118,6 @@ hipError_t spectra_delta(hipStream_t s, int nc, int ch, const double* S, double*
 // ---------------- energy ----------------
 // e = sum rho[P,Q,P',Q'] h[(P',Q'),(P,Q)] / sum rho[P,Q,P,Q];  rho FP64 [p,p,p,p]
 hipError_t bond_energy(hipStream_t s, int p, const double* rho, const double* h, double* e_out);
+hipError_t site_energy(hipStream_t s, int nb, const double* eb, double w, double* out);
 
 }  // namespace sctm

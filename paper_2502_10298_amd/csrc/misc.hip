@@ -543,6 +543,19 @@ hipError_t bond_energy(hipStream_t s, int p, const double* rho, const double* h,
   return hipGetLastError();
 }
 
+// energy per site: the mean over the unit cell's 2 Lx Ly bond energies (each
+// site owns its right and its lower bond), summed in bond order on one lane
+__global__ void site_energy_kernel(int nb, const double* eb, double w, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t = 0.0;
+  for (int i = 0; i < nb; ++i) t += eb[i];
+  out[0] = w * t;
+}
+hipError_t site_energy(hipStream_t s, int nb, const double* eb, double w, double* out) {
+  hipLaunchKernelGGL(site_energy_kernel, dim3(1), dim3(64), 0, s, nb, eb, w, out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // corner-spectrum convergence measure: max_k |S_k - prev_k|_2, then prev = S
 // ---------------------------------------------------------------------------
