@@ -89,20 +89,96 @@ size_t qr_work_bytes(int m, int k, int batch) { return qr_layout(m, k, batch).to
 // product the step needs follows from the raw sums s_l = sum_{i > c} x_ij x_il
 // and the diagonal row c, d_l = x_cl + scale s_l: for l > j the coefficient of
 // the update of column l, for l < j the entry v_l . v_j of T's recurrence,
-// and s_j = |x_below|^2.  The sums go through LDS in two stages.
+// and s_j = |x_below|^2.  Inside a wavefront the PWT partial sums are
+// reduce-scattered by DPP lane exchanges (VALU moves, no LDS), the four 16-lane
+// rows are added by the cross-half lane swaps, the wavefront totals meet in
+// LDS (one barrier per column) and every wavefront adds them in the same
+// order and takes the PWT sums as wavefront-uniform values.
+//
+// DPP controls (16-lane rows): quad_perm [1,0,3,2] = lane ^ 1, [2,3,0,1] =
+// lane ^ 2, row_half_mirror = 7 - lane within eight, row_ror:8 = lane ^ 8,
+// row_ror:4 = lane +- 4 within the row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// lower-half value + upper-half value of the lane pairs (l, l + 32) (HALF =
+// 32) or (l, l + 16) within each 32 (HALF = 16); the same sum in both lanes
+template <int HALF>
+__device__ __forceinline__ double swap_add(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  unsigned lo0, lo1, hi0, hi1;
+  if constexpr (HALF == 32) {
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    lo0 = a[0], lo1 = a[1], hi0 = b[0], hi1 = b[1];
+  } else {
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    lo0 = a[0], lo1 = a[1], hi0 = b[0], hi1 = b[1];
+  }
+  return __builtin_bit_cast(double, ((unsigned long long)hi0 << 32) | lo0) +
+         __builtin_bit_cast(double, ((unsigned long long)hi1 << 32) | lo1);
+}
+
+// One reduce-scatter step over N values: a lane with `up` keeps the upper N/2,
+// the others the lower N/2, and adds the partner's copy of the half it keeps
+// (the partner, selected by CTRL, has the opposite `up` and the same set).
+template <int N, int CTRL, int M>
+__device__ __forceinline__ void rs_step(double (&v)[M], bool up) {
+#pragma unroll
+  for (int q = 0; q < N / 2; ++q) {
+    const double lo = v[q], hi = v[q + N / 2];
+    const double keep = up ? hi : lo, send = up ? lo : hi;
+    v[q] = keep + dpp_f64<CTRL>(send);
+  }
+}
+
+// Wavefront total of v[sel(lane)] for PWT = 16 (sel = 8 b2 + 4 b1 + 2 b0 + b3
+// with b the bits of lane % 16) or PWT = 4 (sel = lane % 4); v is consumed.
+template <int PWT>
+__device__ __forceinline__ int rs_sel(int lane) {
+  if constexpr (PWT == 16)
+    return 8 * ((lane >> 2) & 1) + 4 * ((lane >> 1) & 1) + 2 * (lane & 1) + ((lane >> 3) & 1);
+  else
+    return lane & 3;
+}
+template <int PWT>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[PWT], int lane) {
+  if constexpr (PWT == 16) {
+    rs_step<16, 0x141>(v, (lane >> 2) & 1);   // partner 7 - lane (bit 2 differs)
+    rs_step<8, 0x4E>(v, (lane >> 1) & 1);     // lane ^ 2
+    rs_step<4, 0xB1>(v, lane & 1);            // lane ^ 1
+    rs_step<2, 0x128>(v, (lane >> 3) & 1);    // lane ^ 8
+  } else {
+    static_assert(PWT == 4, "panel widths 16 and 4");
+    rs_step<4, 0x4E>(v, (lane >> 1) & 1);
+    rs_step<2, 0xB1>(v, lane & 1);
+    v[0] = v[0] + dpp_f64<0x124>(v[0]);       // the four quads of the row
+    v[0] = v[0] + dpp_f64<0x128>(v[0]);
+  }
+  return swap_add<16>(swap_add<32>(v[0]));
+}
+
 template <int NT, int RM, int PWT>
 __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr_all, double* T_all,
                                                       double* tau_all, int m, int k, long sX, long sT, int p0,
                                                       int w) {
-  constexpr int NSEG = NT / PWT;   // stage-2 segments of PWT partial rows each
+  constexpr int NW = NT / 64;   // wavefronts
   const int b = blockIdx.x;
   double* Xt = Xt_all + b * sX;
   double* Vr = Vr_all + b * sX;
   double* Tp = T_all + b * sT + (long)(p0 / TSLOT) * PW * PW;
-  const int t = threadIdx.x;
-  __shared__ double buf[NT][PWT + 1];
-  __shared__ double seg[NSEG][PWT + 1];
-  __shared__ double S[PWT];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // wavefront totals and the diagonal row, double-buffered over the columns
+  // (one barrier per column: column j + 2 reuses the buffers of column j only
+  // after every wavefront has passed the barrier of column j + 1)
+  __shared__ double wsum[2][NW][PWT];
   __shared__ double rowc[2][PWT];
   __shared__ double Ts[PW][PW];
   double x[RM][PWT];
@@ -139,23 +215,28 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(double* Xt_all, double* Vr
         for (int l = 0; l < PWT; ++l) rc[l] = x[r][l];
       }
     }
-#pragma unroll
-    for (int l = 0; l < PWT; ++l) buf[t][l] = part[l];
-    __syncthreads();
     {
-      const int l = t % PWT, g = t / PWT;
+      const double tot = wave_reduce_scatter<PWT>(part, lane);
+      if (lane < PWT) wsum[j & 1][wv][rs_sel<PWT>(lane)] = tot;
+    }
+    __syncthreads();
+    // lane l < PWT adds the wavefront totals of s_l in wavefront order; S[l]
+    // is then read from that lane (the same value in every wavefront)
+    double S[PWT];
+    {
       double a = 0.0;
+      if (lane < PWT) {
 #pragma unroll
-      for (int q = 0; q < PWT; ++q) a += buf[g * PWT + q][l];
-      seg[g][l] = a;
+        for (int q = 0; q < NW; ++q) a += wsum[j & 1][q][lane];
+      }
+      const unsigned long long u = __builtin_bit_cast(unsigned long long, a);
+#pragma unroll
+      for (int l = 0; l < PWT; ++l) {
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+        S[l] = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+      }
     }
-    __syncthreads();
-    if (t < PWT) {
-      double a = 0.0;
-      for (int g = 0; g < NSEG; ++g) a += seg[g][t];
-      S[t] = a;
-    }
-    __syncthreads();
     const double sq = S[j], x0 = rc[j];
     double tau = 0.0, beta = x0, scale = 0.0;
     if (sq > 0.0) {
@@ -236,15 +317,34 @@ __global__ __launch_bounds__(256) void qr_rowprod_partial_kernel(const double* A
   const int c0 = ch * SCH;
   __shared__ double As[NBW][SCH + 1];
   __shared__ double Bs[SAME ? 1 : NBR][SCH + 1];
-  for (int e = tid; e < NBW * SCH; e += 256) {
-    const int r = e / SCH, c = e % SCH;
-    As[r][c] = (r < na && c0 + c < len) ? A[(long)r * ld + c0 + c] : 0.0;
+  // every staging load is issued before the first LDS store, so that their
+  // latencies overlap
+  constexpr int LA = NBW * SCH / 256, LB = SAME ? 1 : NBR * SCH / 256;
+  double va[LA], vb[LB];
+#pragma unroll
+  for (int q = 0; q < LA; ++q) {
+    const int e = tid + 256 * q, r = e / SCH, c = e % SCH;
+    va[q] = (r < na && c0 + c < len) ? A[(long)r * ld + c0 + c] : 0.0;
   }
-  if (!SAME)
-    for (int e = tid; e < NBR * SCH; e += 256) {
-      const int r = e / SCH, c = e % SCH;
-      Bs[r][c] = (r < nb && c0 + c < len) ? B[(long)r * ld + c0 + c] : 0.0;
+  if (!SAME) {
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + 256 * q, r = e / SCH, c = e % SCH;
+      vb[q] = (r < nb && c0 + c < len) ? B[(long)r * ld + c0 + c] : 0.0;
     }
+  }
+#pragma unroll
+  for (int q = 0; q < LA; ++q) {
+    const int e = tid + 256 * q;
+    As[e / SCH][e % SCH] = va[q];
+  }
+  if (!SAME) {
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + 256 * q;
+      Bs[e / SCH][e % SCH] = vb[q];
+    }
+  }
   __syncthreads();
   if (wv * 16 >= na) return;   // no rows for this wave (uniform)
   const int ntile = SAME ? NBW / 16 : 1;
@@ -339,63 +439,59 @@ __global__ __launch_bounds__(1024) void qr_tblock_kernel(const double* P_all, in
 // In-block update: Y <- Y - (W T) V for the nt <= 64 rows of Y (length len,
 // leading dimension ld), V the panel's pw <= 16 reflector rows, T its
 // triangular factor (PW x PW) and W = Y V^T the sum of the chunk partials.
-// One workgroup per 256 entries of the length (thread = one entry).
-__global__ __launch_bounds__(256) void qr_inblock_apply_kernel(double* Y_all, long sY, int nt, int len, int ld,
-                                                               const double* V_all, long sV, int pw,
-                                                               const double* P_all, int nch, const double* T_all,
-                                                               long sT) {
-  const int b = blockIdx.y;
+// Grid: (chunk of IB_T entries of the length) x batch x (group of IB_R rows
+// of Y), so that a small batch still spreads over the chip; a workgroup sums
+// the partials of its IB_R rows of W (in chunk order), forms their W T and
+// applies them to its entries (thread = one entry).
+static constexpr int IB_T = 128, IB_R = 8;
+__global__ __launch_bounds__(IB_T) void qr_inblock_apply_kernel(double* Y_all, long sY, int nt, int len, int ld,
+                                                                const double* V_all, long sV, int pw,
+                                                                const double* P_all, int nch, const double* T_all,
+                                                                long sT) {
+  static_assert(IB_R * PW == IB_T, "one W entry per thread");
+  const int b = blockIdx.y, r0 = blockIdx.z * IB_R;
   double* Y = Y_all + b * sY;
   const double* V = V_all + b * sV;
   const double* P = P_all + (long)b * nch * NBW * NBW;
   const double* T = T_all + b * sT;
   const int tid = threadIdx.x;
-  __shared__ double Wm[NBW][PW + 1];
-  __shared__ double W2[NBW][PW + 1];
+  __shared__ double Wm[IB_R][PW + 1];
+  __shared__ double W2[IB_R][PW + 1];
   __shared__ double Ts[PW][PW + 1];
   {
-    double acc[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] = 0.0;
+    const int r = r0 + tid / PW, c = tid % PW;
+    const bool in = r < nt && c < pw;
+    double acc = 0.0;
     for (int ch0 = 0; ch0 < nch; ch0 += 8) {
-      double v[8][4];
+      double v[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
+        v[q] = (ch0 + q < nch && in) ? P[(long)(ch0 + q) * NBW * NBW + r * NBW + c] : 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int e = tid + 256 * i, r = e / PW, c = e % PW;
-          v[q][i] = (ch0 + q < nch && r < nt && c < pw) ? P[(long)(ch0 + q) * NBW * NBW + r * NBW + c] : 0.0;
-        }
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] += v[q][i];
+      for (int q = 0; q < 8; ++q) acc += v[q];
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = tid + 256 * i;
-      Wm[e / PW][e % PW] = acc[i];
-    }
+    Wm[tid / PW][c] = acc;
   }
-  for (int e = tid; e < PW * PW; e += 256) Ts[e / PW][e % PW] = T[e];
+  for (int e = tid; e < PW * PW; e += IB_T) Ts[e / PW][e % PW] = T[e];
   __syncthreads();
-  for (int e = tid; e < NBW * PW; e += 256) {
-    const int r = e / PW, c = e % PW;
+  {
+    const int r = tid / PW, c = tid % PW;
     double a = 0.0;
     for (int j = 0; j < pw; ++j) a += Wm[r][j] * Ts[j][c];
     W2[r][c] = (c < pw) ? a : 0.0;
   }
   __syncthreads();
-  const int i = blockIdx.x * 256 + tid;
+  const int i = blockIdx.x * IB_T + tid;
   if (i >= len) return;
   double v[PW];
 #pragma unroll
   for (int c = 0; c < PW; ++c) v[c] = (c < pw) ? V[(long)c * ld + i] : 0.0;
-  for (int r = 0; r < nt; ++r) {
+  const int nr = min(IB_R, nt - r0);
+  for (int r = 0; r < nr; ++r) {
     double a = 0.0;
 #pragma unroll
     for (int c = 0; c < PW; ++c) a += W2[r][c] * v[c];
-    Y[(long)r * ld + i] -= a;
+    Y[(long)(r0 + r) * ld + i] -= a;
   }
 }
 
@@ -414,13 +510,30 @@ __global__ __launch_bounds__(256) void qr_w2_kernel(const double* P_all, int S, 
   const int tid = threadIdx.x, row0 = blockIdx.x * 16;
   __shared__ double Ts[NBW][NBW + 1];
   __shared__ double Ws[16][NBW + 1];
-  for (int e = tid; e < NBW * NBW; e += 256) Ts[e / NBW][e % NBW] = TB[e];
+  // all loads (T, then every slice of this thread's entries) are issued
+  // before the first LDS store
+  double tv[NBW * NBW / 256], pv[4][QR_SMAX];
+#pragma unroll
+  for (int q = 0; q < NBW * NBW / 256; ++q) tv[q] = TB[tid + 256 * q];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int e = tid + 256 * i, r = e / NBW, c = e % NBW;
     const bool ok = row0 + r < nt && c < nv;
+#pragma unroll
+    for (int sl = 0; sl < QR_SMAX; ++sl) pv[i][sl] = (ok && sl < S) ? P[sl * snn + (long)(row0 + r) * nv + c] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NBW * NBW / 256; ++q) {
+    const int e = tid + 256 * q;
+    Ts[e / NBW][e % NBW] = tv[q];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = tid + 256 * i, r = e / NBW, c = e % NBW;
     double a = 0.0;
-    for (int sl = 0; sl < S; ++sl) a += ok ? P[sl * snn + (long)(row0 + r) * nv + c] : 0.0;
+#pragma unroll
+    for (int sl = 0; sl < QR_SMAX; ++sl)
+      if (sl < S) a += pv[i][sl];
     Ws[r][c] = a;
   }
   __syncthreads();
@@ -546,7 +659,8 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
                          L.sX, nt, Vp, L.sX, pw, rows, m, Pb, nch);
       e = hipGetLastError();
       if (e != hipSuccess) break;
-      hipLaunchKernelGGL(qr_inblock_apply_kernel, dim3((rows + 255) / 256, batch), dim3(256), 0, s, Y, L.sX, nt, rows,
+      hipLaunchKernelGGL(qr_inblock_apply_kernel, dim3((rows + IB_T - 1) / IB_T, batch, (nt + IB_R - 1) / IB_R),
+                         dim3(IB_T), 0, s, Y, L.sX, nt, rows,
                          m, Vp, L.sX, pw, (const double*)Pb, nch,
                          (const double*)(T + (long)(p0 / TSLOT) * PW * PW), L.sT);
       e = hipGetLastError();

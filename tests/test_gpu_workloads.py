@@ -536,3 +536,66 @@ def test_config_d2_D10_chi160_gradient_60_sweeps_recompute():
           f"gradient max diff {float((g5 - g10).abs().max()):.1e}")
     assert abs(e5 - e10) <= 1e-12 * abs(e10)
     assert torch.allclose(g5, g10, atol=1e-10 * float(g10.abs().max()), rtol=0)
+
+
+@pytest.mark.parametrize("p,D", [(2, 6), (4, 4)])
+def test_scaling_chi170_column_parity_fp64(p, D):
+    """Parity at the sizes of the sweep-time scaling runs (1x1 cell of a
+    seeded Gaussian tensor, chi_E = chi_I = 170): from the environment after
+    the two BF16x3 sweeps from the identity boundary that those runs leave
+    untimed, the FP64 path's projector pairs of column 0 of the left move and
+    its new C1, T4k, T4b, C4 equal the oracle's element by element, with the
+    gap-derived bound of the headline column test (100 eps s_1 / g_min, at
+    least 1e-9), and for p = 2 the vertical bond energy after the column
+    agrees to 1e-10 relative.  chi D = 1020 and 680 are not multiples of the
+    Jacobi's 16-column blocks, so the padded tail of the SVD runs at its real
+    shape; p = 4 widens the red projectors' physical leg."""
+    chi = 170
+    A_np = inp.peps_gaussian(700 + D, 1, 1, p, D)
+    _say(f"scaling size p={p} D={D} chi={chi}: two BF16x3 sweeps from the identity boundary")
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, chi, prec="bf16x3")
+    obj.sweep(2)
+    flat = obj.env_export()
+    obj.close()
+    _say(f"scaling size p={p} D={D}: FP64 projectors and column 0 of the left move")
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), chi, chi, prec="fp64")
+    obj.env_import(flat)
+    P, _ = obj.projectors(0, 0, 0)
+    P = {k: v.cpu().numpy() for k, v in P.items()}
+    obj.move_column(0, 0)
+    out = obj.env_export().cpu().numpy()
+    h = inp.heisenberg_h()
+    bonds = obj.energy(h)[1] if p == 2 else None
+    obj.close()
+    new = inp.unpack_env(out, 1, 1, D, chi, chi)
+    _say(f"scaling size p={p} D={D}: oracle column")
+    env = sc.env_from_numpy(inp.unpack_env(flat.cpu().numpy(), 1, 1, D, chi, chi))
+    A = sc.peps_from_numpy(A_np)
+    with torch.no_grad():
+        G, Y, TH, R, _ = sc.column_projectors(env, A, 1, 1, 0, chi, chi)
+        sc.left_move_column(env, A, 1, 1, 0, chi, chi)
+        e_ref = float(sc.bond_value(sc.rdm_vertical(env, A, 0, 0, 1, 1), h)) if p == 2 else None
+    errs, bounds = {}, {}
+    for nm, prs in {"green": G, "teal": TH, "yellow": Y, "red": R}.items():
+        pr = prs[0]
+        k = pr[3]
+        S = pr[2].numpy()
+        gap = float(np.min(-np.diff(S[: k + 1]))) if k < len(S) else float(np.min(-np.diff(S[:k])))
+        bounds[nm] = max(1e-9, 100 * 2.2e-16 * float(S[0]) / gap)
+        for j, side in ((0, "_T"), (1, "_B")):
+            r = pr[j].numpy()
+            got = P[nm + side][..., :k].reshape(r.shape)
+            errs[nm + side] = float(np.abs(got - r).max() / np.abs(r).max())
+            assert errs[nm + side] <= bounds[nm], (nm, side, errs[nm + side], bounds[nm])
+        tail = P[nm + "_T"][..., k:]
+        assert tail.size == 0 or float(np.abs(tail).max()) == 0.0
+    for t in ("C1", "T4k", "T4b", "C4"):
+        r = env[(0, 0)][t].numpy()
+        errs[t] = float(np.abs(new[(0, 0)][t] - r).max() / np.abs(r).max())
+    print(f"[result] chi=170 p={p} D={D}, FP64 column vs oracle:", {k: f"{v:.1e}" for k, v in errs.items()},
+          "gap bounds:", {k: f"{v:.1e}" for k, v in bounds.items()})
+    assert max(errs[t] for t in ("C1", "T4k", "T4b", "C4")) <= max(bounds.values())
+    if p == 2:
+        e_gpu = float(bonds[0, 0, 1])
+        print(f"[result] chi=170 D={D} vertical bond after the column: {e_gpu:.15e} vs {e_ref:.15e}")
+        assert abs(e_gpu - e_ref) <= 1e-10 * abs(e_ref)
