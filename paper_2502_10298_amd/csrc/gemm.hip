@@ -76,7 +76,7 @@ __device__ inline void load_b(const T* __restrict__ B, long ldb, int N, int K, i
   }
 }
 
-template <typename T, typename V4, bool TA, bool TB>
+template <typename T, typename V4, bool TA, bool TB, bool BETA>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
                                                    const T* __restrict__ A, long lda, long sA,
                                                    const T* __restrict__ B, long ldb, long sB, T beta,
@@ -101,6 +101,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
+  // BETA (beta != 0): the sixteen C entries of the thread are loaded first
+  // (clamped addresses, no branches), so that their latency overlaps the
+  // operand loads and the MFMAs instead of following the last k tile.
+  T cold[2][2][4];
+  if (BETA) {
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = sizeof(T) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+          const int m = min(bm + wm * 32 + ti * 16 + row, M - 1), n = min(bn + wn * 32 + tj * 16 + (lane & 15), N - 1);
+          cold[ti][tj][r] = C[(long)m * ldc + n];
+        }
+  }
   T ra[8], rb[8];
   load_a<T, TA>(A, lda, M, K, bm, 0, tid, ra);
   load_b<T, TB>(B, ldb, N, K, bn, 0, tid, rb);
@@ -132,21 +148,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
     __syncthreads();
   }
   // f64 16x16x4: D[4 r + l / 16][l % 16]; f32 16x16x4: D[4 (l / 16) + r][l % 16].
-  // With beta != 0 all sixteen C entries of the thread are loaded (clamped
-  // addresses, no branches) before any is combined, so their latencies overlap.
-  T cold[2][2][4];
-  if (beta != T(0)) {
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = sizeof(T) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
-          const int m = min(bm + wm * 32 + ti * 16 + row, M - 1), n = min(bn + wn * 32 + tj * 16 + (lane & 15), N - 1);
-          cold[ti][tj][r] = C[(long)m * ldc + n];
-        }
-  }
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
         if (m < M && n < N) {
           T v = alpha * acc[ti][tj][r];
           long o = (long)m * ldc + n;
-          C[o] = (beta == T(0)) ? v : v + beta * cold[ti][tj][r];
+          C[o] = BETA ? v + beta * cold[ti][tj][r] : v;
         }
       }
 }
@@ -293,6 +294,18 @@ static dim3 gemm_grid(int M, int N, int batch) {
   return dim3((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
 }
 
+template <typename T, typename V4, bool TA, bool TB>
+static void launch_gemm(int kind, double fl, double by, dim3 g, hipStream_t s, int M, int N, int K, T alpha,
+                        const T* A, long lda, long sA, const T* B, long ldb, long sB, T beta, T* C, long ldc, long sC,
+                        int zdiv, long sA2, long sB2, long sC2, int Ktot) {
+  if (beta != T(0))
+    launch_timed(kind, fl, by, gemm_kernel<T, V4, TA, TB, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
+                 ldb, sB, beta, C, ldc, sC, zdiv, sA2, sB2, sC2, Ktot);
+  else
+    launch_timed(kind, fl, by, gemm_kernel<T, V4, TA, TB, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
+                 ldb, sB, beta, C, ldc, sC, zdiv, sA2, sB2, sC2, Ktot);
+}
+
 KernelTimer*& kernel_timer() {
   static thread_local KernelTimer* t = nullptr;
   return t;
@@ -307,13 +320,13 @@ hipError_t gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double
   const double fl = 2.0 * M * N * (double)K * batch;
   const double by = 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1));
   if (!tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
+    launch_gemm<double, d4, false, false>(kind, fl, by, g, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else if (tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
+    launch_gemm<double, d4, true, false>(kind, fl, by, g, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else if (!tA && tB)
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
+    launch_gemm<double, d4, false, true>(kind, fl, by, g, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
+    launch_gemm<double, d4, true, true>(kind, fl, by, g, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   return hipGetLastError();
 }
 
@@ -329,16 +342,16 @@ hipError_t gemm_f64_slices(hipStream_t s, bool tA, bool tB, int M, int N, int K,
   const long sA2 = tA ? (long)Ks * lda : Ks, sB2 = tB ? (long)Ks : (long)Ks * ldb;
   const long sP = (long)S * M * N, sP2 = (long)M * N;
   if (!tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, false>, g, dim3(256), 0, s, M, N, Ks, 1.0, A, lda, sA, B,
+    launch_gemm<double, d4, false, false>(kind, fl, by, g, s, M, N, Ks, 1.0, A, lda, sA, B,
                  ldb, sB, 0.0, P, (long)N, sP, S, sA2, sB2, sP2, K);
   else if (tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, false>, g, dim3(256), 0, s, M, N, Ks, 1.0, A, lda, sA, B,
+    launch_gemm<double, d4, true, false>(kind, fl, by, g, s, M, N, Ks, 1.0, A, lda, sA, B,
                  ldb, sB, 0.0, P, (long)N, sP, S, sA2, sB2, sP2, K);
   else if (!tA && tB)
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, false, true>, g, dim3(256), 0, s, M, N, Ks, 1.0, A, lda, sA, B,
+    launch_gemm<double, d4, false, true>(kind, fl, by, g, s, M, N, Ks, 1.0, A, lda, sA, B,
                  ldb, sB, 0.0, P, (long)N, sP, S, sA2, sB2, sP2, K);
   else
-    launch_timed(kind, fl, by, gemm_kernel<double, d4, true, true>, g, dim3(256), 0, s, M, N, Ks, 1.0, A, lda, sA, B,
+    launch_gemm<double, d4, true, true>(kind, fl, by, g, s, M, N, Ks, 1.0, A, lda, sA, B,
                  ldb, sB, 0.0, P, (long)N, sP, S, sA2, sB2, sP2, K);
   return hipGetLastError();
 }
@@ -373,13 +386,13 @@ hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, in
     return hipGetLastError();
   }
   if (!tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<float, f4, false, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
+    launch_gemm<float, f4, false, false>(kind, fl, by, g, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else if (tA && !tB)
-    launch_timed(kind, fl, by, gemm_kernel<float, f4, true, false>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
+    launch_gemm<float, f4, true, false>(kind, fl, by, g, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else if (!tA && tB)
-    launch_timed(kind, fl, by, gemm_kernel<float, f4, false, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
+    launch_gemm<float, f4, false, true>(kind, fl, by, g, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   else
-    launch_timed(kind, fl, by, gemm_kernel<float, f4, true, true>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
+    launch_gemm<float, f4, true, true>(kind, fl, by, g, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, 1, 0L, 0L, 0L, K);
   return hipGetLastError();
 }
 

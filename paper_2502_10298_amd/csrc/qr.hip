@@ -35,7 +35,7 @@ namespace sctm {
 static constexpr int PW = 16;     // widest panel (T blocks are PW x PW)
 static constexpr int TSLOT = 4;   // narrowest panel: one T block per TSLOT columns
 static constexpr int NBW = 64;    // columns per outer block
-static constexpr int QR_SMAX = 4;  // K slices of the W = Y V^T products at most
+static constexpr int QR_SMAX = 8;  // K slices of the W = Y V^T products at most
 
 // f(integral_constant<int, J>) for J = Js... in order
 template <typename F, int... Js>
@@ -570,11 +570,12 @@ __global__ void qr_eye_kernel(double* Qt_all, int m, int k, long sX) {
 
 static int grid_of(long n) { return (int)std::min<long>((n + 255) / 256, 4096); }
 
-// K slices of W = Y V^T: enough workgroups to fill the chip, slices of at
+// K slices of W = Y V^T: about four workgroups per compute unit (the
+// product streams Y once, so it needs many loads in flight), slices of at
 // least 256 entries
 static int w_slices(int nt, int len, int batch) {
   const int tiles = (nt + 63) / 64;
-  int S = (384 + tiles * batch - 1) / (tiles * batch);
+  int S = (1024 + tiles * batch - 1) / (tiles * batch);
   S = std::min(S, std::min(QR_SMAX, len / 256));
   return std::max(S, 1);
 }
