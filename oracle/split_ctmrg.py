@@ -130,7 +130,7 @@ def projectors(rhoT: torch.Tensor, rhoB: torch.Tensor, n_a: int, chi: int,
     RB = rhoB.reshape(na, -1)
     M = RB.T @ RT
     U, S, V = broadened_svd(M, adj_eps)
-    s1 = float(S[0]) if S.numel() else 0.0
+    s1 = float(S[0].detach()) if S.numel() else 0.0
     if not (s1 > 0.0) or not math.isfinite(s1):
         raise RankZero("projector matrix has rank zero or is not finite")
     k = min(chi, int((S > cutoff * s1).sum()))

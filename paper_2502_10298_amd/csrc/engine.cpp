@@ -227,13 +227,24 @@ void Engine::gemm(bool tA, bool tB, int M, int N, int K, double alpha, const Ten
     gemm_route(tA, tB, M, N, K, alpha, A, offA, lda, B, offB, ldb, beta, C, offC, ldc);
     return;
   }
+  // us: device time of the product's kernels (events on the stream); host_us:
+  // the same on the host clock, with launch and synchronisation overheads
+  static hipEvent_t ev[2] = {nullptr, nullptr};
+  if (!ev[0]) {
+    check(hipEventCreate(&ev[0]));
+    check(hipEventCreate(&ev[1]));
+  }
   check(hipStreamSynchronize(s));
   const auto t0 = std::chrono::steady_clock::now();
+  check(hipEventRecord(ev[0], s));
   const char* route = gemm_route(tA, tB, M, N, K, alpha, A, offA, lda, B, offB, ldb, beta, C, offC, ldc);
+  check(hipEventRecord(ev[1], s));
   check(hipStreamSynchronize(s));
-  const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-  fprintf(stderr, "[gemm] route=%s dt=%d tA=%d tB=%d M=%d N=%d K=%d lda=%ld ldb=%ld ldc=%ld beta=%g us=%.1f\n", route,
-          C.dt, (int)tA, (int)tB, M, N, K, lda, ldb, ldc, beta, us);
+  const double hus = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  float ms = 0.f;
+  check(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  fprintf(stderr, "[gemm] route=%s dt=%d tA=%d tB=%d M=%d N=%d K=%d lda=%ld ldb=%ld ldc=%ld beta=%g us=%.1f host_us=%.1f\n",
+          route, C.dt, (int)tA, (int)tB, M, N, K, lda, ldb, ldc, beta, 1e3 * ms, hus);
 }
 
 const char* Engine::gemm_route(bool tA, bool tB, int M, int N, int K, double alpha, const Ten& A, long offA,

@@ -290,6 +290,119 @@ __global__ __launch_bounds__(256) void gemm_bf16s_kernel(int M, int N, int K, fl
       }
 }
 
+// Split BF16 products with K <= 128 on a small grid (the short contractions
+// and the K slices of split-K products): the whole k extent of both operand
+// tiles is loaded at once (one memory round trip instead of one per 32-wide k tile), split into
+// LDS, and the MFMAs run after a single barrier.  Same lane layouts, term
+// order and FP32 accumulation order as gemm_bf16s_kernel.
+static constexpr int SKM = 128;   // largest K of the short-product kernel
+
+template <bool TA, bool TB, int NS>
+__global__ __launch_bounds__(256) void gemm_bf16s_shortk_kernel(int M, int N, int K, float alpha,
+                                                                const float* __restrict__ A, long lda, long sA,
+                                                                const float* __restrict__ B, long ldb, long sB,
+                                                                float beta, float* __restrict__ C, long ldc, long sC) {
+  constexpr int BK = 32, NKT = SKM / BK;
+  __shared__ __attribute__((aligned(16))) __bf16 As[NS][BM][SKM + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][BN][SKM + 8];
+  const long bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  const int bm = blockIdx.y * BM, bn = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int nkt = (K + BK - 1) / BK;   // <= NKT
+  float ra[NKT][8], rb[NKT][8];
+#pragma unroll
+  for (int kt = 0; kt < NKT; ++kt) {
+    if (kt < nkt) {
+      load_a<float, TA>(A, lda, M, K, bm, kt * BK, tid, ra[kt]);
+      load_b<float, TB>(B, ldb, N, K, bn, kt * BK, tid, rb[kt]);
+    }
+  }
+  float cold[2][2][4];
+  if (beta != 0.f) {
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = min(bm + wm * 32 + ti * 16 + 4 * (lane >> 4) + r, M - 1);
+          const int n = min(bn + wn * 32 + tj * 16 + (lane & 15), N - 1);
+          cold[ti][tj][r] = C[(long)m * ldc + n];
+        }
+  }
+#pragma unroll
+  for (int kt = 0; kt < NKT; ++kt) {
+    if (kt >= nkt) break;
+    __bf16 sp[NS];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      split_bf16<NS>(ra[kt][i], sp);
+      if (!TA) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) As[q][(tid >> 5) + 8 * i][kt * BK + (tid & 31)] = sp[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) As[q][tid & 63][kt * BK + (tid >> 6) + 4 * i] = sp[q];
+      }
+      split_bf16<NS>(rb[kt][i], sp);
+      if (!TB) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) Bs[q][tid & 63][kt * BK + (tid >> 6) + 4 * i] = sp[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) Bs[q][(tid >> 5) + 8 * i][kt * BK + (tid & 31)] = sp[q];
+      }
+    }
+  }
+  __syncthreads();
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
+#pragma unroll
+  for (int kt = 0; kt < NKT; ++kt) {
+    if (kt >= nkt) break;
+    const int kq = kt * BK + 8 * (lane >> 4);
+    bf8 a[NS][2], bb[NS][2];
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[q][t] = *reinterpret_cast<const bf8*>(&As[q][wm * 32 + t * 16 + (lane & 15)][kq]);
+        bb[q][t] = *reinterpret_cast<const bf8*>(&Bs[q][wn * 32 + t * 16 + (lane & 15)][kq]);
+      }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+#pragma unroll
+        for (int o = NS - 1; o >= 0; --o)
+#pragma unroll
+          for (int qa = o; qa >= 0; --qa)
+            acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[qa][ti], bb[o - qa][tj], acc[ti][tj], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int m = bm + wm * 32 + ti * 16 + 4 * (lane >> 4) + r;
+        int n = bn + wn * 32 + tj * 16 + (lane & 15);
+        if (m < M && n < N) {
+          float v = alpha * acc[ti][tj][r];
+          long o = (long)m * ldc + n;
+          C[o] = (beta == 0.f) ? v : v + beta * cold[ti][tj][r];
+        }
+      }
+}
+
 static dim3 gemm_grid(int M, int N, int batch) {
   return dim3((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
 }
@@ -366,8 +479,19 @@ hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, in
   const double by = 4.0 * batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.f ? 2 : 1));
   if (mode == Prec::BF16X3 || mode == Prec::BF16X6) {
     const bool six = mode == Prec::BF16X6;
+    // short products on a small grid: one memory round trip per workgroup;
+    // on a large grid the pipelined kernel (less LDS, more workgroups per
+    // compute unit) is faster
+    const bool shortk = K <= SKM && (long)g.x * g.y * g.z <= 512;
 #define SPLIT_LAUNCH(TA_, TB_)                                                                                      \
-  if (six)                                                                                                           \
+  if (shortk) {                                                                                                      \
+    if (six)                                                                                                         \
+      launch_timed(kind, fl, by, gemm_bf16s_shortk_kernel<TA_, TB_, 3>, g, dim3(256), 0, s, M, N, K, alpha, A, lda,  \
+                   sA, B, ldb, sB, beta, C, ldc, sC);                                                                \
+    else                                                                                                             \
+      launch_timed(kind, fl, by, gemm_bf16s_shortk_kernel<TA_, TB_, 2>, g, dim3(256), 0, s, M, N, K, alpha, A, lda,  \
+                   sA, B, ldb, sB, beta, C, ldc, sC);                                                                \
+  } else if (six)                                                                                                    \
     launch_timed(kind, fl, by, gemm_bf16s_kernel<TA_, TB_, 3>, g, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, \
                  sB, beta, C, ldc, sC);                                                                              \
   else                                                                                                               \
@@ -404,7 +528,7 @@ hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, in
 static int splitk_slices(int M, int N, int K) {
   const long tiles = (long)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   if (M <= 0 || N <= 0 || tiles >= 128 || K < 1024) return 0;
-  int S = (int)std::min<long>(std::min<long>(512 / tiles, K / 256), 64);
+  int S = (int)std::min<long>(std::min<long>(512 / tiles, K / 128), 64);
   while (S > 1 && (long)S * M * N > (16L << 20)) S /= 2;
   return S >= 2 ? S : 0;
 }

@@ -27,7 +27,8 @@ def _say(*a):
 # kernels
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16x3", 4e-5), ("bf16x6", 2e-6)])
-@pytest.mark.parametrize("shape", [(70, 45, 33), (300, 260, 190), (1, 129, 64), (257, 3, 1000)])
+@pytest.mark.parametrize("shape", [(70, 45, 33), (300, 260, 190), (1, 129, 64), (257, 3, 1000), (200, 150, 128),
+                                   (130, 70, 97), (2100, 1100, 100)])
 @pytest.mark.parametrize("tA,tB", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm(prec, tol, shape, tA, tB):
     M, N, K = shape
