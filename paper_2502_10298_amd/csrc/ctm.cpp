@@ -5,7 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -791,6 +794,31 @@ double corner_delta(ctm_ctx* c) {
 // ---------------------------------------------------------------------------
 // gradient: forward with checkpoints, then reverse move by move
 // ---------------------------------------------------------------------------
+// SPLITCTM_PHASES (diagnostics): the stream is synchronised at the phase
+// boundaries of energy_grad and the host time of each phase is printed
+// (forward sweeps, energy with its reverse, taped recompute of the moves,
+// reverse of the moves).
+struct PhaseClock {
+  bool on = getenv("SPLITCTM_PHASES") != nullptr;
+  double acc[4] = {0, 0, 0, 0};
+  std::chrono::steady_clock::time_point t0;
+  void start(Engine& E) {
+    if (!on || E.dry) return;
+    E.check(hipStreamSynchronize(E.s));
+    t0 = std::chrono::steady_clock::now();
+  }
+  void stop(Engine& E, int k) {
+    if (!on || E.dry) return;
+    E.check(hipStreamSynchronize(E.s));
+    acc[k] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  void report(bool dry) const {
+    if (on && !dry)
+      fprintf(stderr, "[phases] forward %.3f s, energy %.3f s, taped recompute %.3f s, reverse %.3f s\n", acc[0],
+              acc[1], acc[2], acc[3]);
+  }
+};
+
 ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_host, int n_sweeps, int ckpt,
                             double* e_site, double* dA_dev) {
   Engine& E = c->E;
@@ -833,6 +861,8 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_h
     E.check(hipMemcpyAsync(ck[0].p, c->start_blk.p, c->start_blk.bytes(), hipMemcpyDeviceToDevice, E.s));
   }
   const Peps A = peps_view(*c, c->Aflat);
+  PhaseClock pc;
+  pc.start(E);
   // ---- forward: store the environment at the start of every block ----
   for (int s = 0; s < n_sweeps && E.ok(); ++s) {
     if (s % ckpt == 0 && s > 0) {
@@ -865,6 +895,8 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_h
   // ckpt sweeps), restored into the current environment at the end
   if (nblk > 0 && !E.dry && E.ok())
     E.check(hipMemcpyAsync(ck[nblk].p, c->cur_blk.p, c->cur_blk.bytes(), hipMemcpyDeviceToDevice, E.s));
+  pc.stop(E, 0);
+  pc.start(E);
   // ---- energy (taped) and its reverse pass -> cotangent of the final env ----
   double esum = 0.0;
   {
@@ -905,6 +937,7 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_h
     E.clear_tape();
     E.ar.release(mk);
   }
+  pc.stop(E, 1);
   if (e_site) *e_site = esum;
   if (!std::isfinite(esum) && !E.dry) return CTM_ENUMERIC;
   // ---- reverse over blocks and moves ----
@@ -945,10 +978,13 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_h
         t.id = E.next_id++;
         E.mark_input(t);
       }
+      pc.start(E);
       E.svdc_select(m, 2);
       Env out = do_move(*c, env, Ai, dir);
       E.svdc_select(-1, 0);
       E.taping = false;
+      pc.stop(E, 2);
+      pc.start(E);
       // seed with the cotangent of the move's output
       Env gv = view_env(*c, genv);
       for (size_t s = 0; s < out.s.size(); ++s)
@@ -970,10 +1006,12 @@ ctm_status energy_grad_impl(ctm_ctx* c, const double* h_host, const double* hv_h
       }
       E.clear_tape();
       E.ar.release(mk);
+      pc.stop(E, 3);
       if (E.dry) break;
     }
     if (E.dry) break;
   }
+  pc.report(E.dry);
   // leave the current environment at the state after n_sweeps
   if (!E.dry && E.ok() && nblk > 0)
     E.check(hipMemcpyAsync(c->cur_blk.p, ck[nblk].p, ck[nblk].bytes(), hipMemcpyDeviceToDevice, E.s));

@@ -523,11 +523,11 @@ hipError_t gemm_f32(hipStream_t s, Prec mode, bool tA, bool tB, int M, int N, in
 
 // ---------------------------------------------------------------------------
 // Split-K: a product whose 64 x 64 output tiles are too few to fill the chip
-// and whose K is long runs as a strided batch of K slices into a scratch
+// and whose K is long (>= 512) runs as a strided batch of K slices into a scratch
 // buffer; one more pass adds the slices in order and applies alpha and beta.
 static int splitk_slices(int M, int N, int K) {
   const long tiles = (long)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  if (M <= 0 || N <= 0 || tiles >= 128 || K < 1024) return 0;
+  if (M <= 0 || N <= 0 || tiles >= 128 || K < 512) return 0;
   int S = (int)std::min<long>(std::min<long>(512 / tiles, K / 128), 64);
   while (S > 1 && (long)S * M * N > (16L << 20)) S /= 2;
   return S >= 2 ? S : 0;
@@ -602,10 +602,10 @@ typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 // thread splits eight consecutive k of one row and writes them as one
 // 16-byte vector per plane.
 template <bool TRANS>
-__global__ __launch_bounds__(256) void bf16_split_kernel(const float* __restrict__ X, long ld, int R, int K, int Kp,
-                                                         __bf16* __restrict__ H, __bf16* __restrict__ L) {
-  __shared__ float tile[64][65];   // [r][k]
-  const int r0 = blockIdx.y * 64, k0 = blockIdx.x * 64, t = threadIdx.x;
+__device__ __forceinline__ void bf16_split_tile(const float* __restrict__ X, long ld, int R, int K, int Kp,
+                                                __bf16* __restrict__ H, __bf16* __restrict__ L, int r0, int k0,
+                                                float (&tile)[64][65]) {
+  const int t = threadIdx.x;
   // all sixteen loads in flight before the first LDS write; out-of-range
   // entries read an in-range one (clamped, no branch) and count as zero
   float v[16];
@@ -641,6 +641,21 @@ __global__ __launch_bounds__(256) void bf16_split_kernel(const float* __restrict
     *reinterpret_cast<bf8*>(H + o) = hi;
     *reinterpret_cast<bf8*>(L + o) = lo;
   }
+}
+
+// Both operands of a product in one launch: grid (Kp / 64, RpA / 64 + RpB / 64),
+// the first RpA / 64 rows of workgroups split A, the rest B.
+template <bool TRANSA, bool TRANSB>
+__global__ __launch_bounds__(256) void bf16_split2_kernel(const float* __restrict__ A, long lda, int RA, int RpA,
+                                                          const float* __restrict__ B, long ldb, int RB, int K, int Kp,
+                                                          __bf16* __restrict__ AH, __bf16* __restrict__ AL,
+                                                          __bf16* __restrict__ BH, __bf16* __restrict__ BL) {
+  __shared__ float tile[64][65];   // [r][k]
+  const int by = blockIdx.y, k0 = blockIdx.x * 64;
+  if (by * 64 < RpA)
+    bf16_split_tile<TRANSA>(A, lda, RA, K, Kp, AH, AL, by * 64, k0, tile);
+  else
+    bf16_split_tile<TRANSB>(B, ldb, RB, K, Kp, BH, BL, by * 64 - RpA, k0, tile);
 }
 
 // Slice z of the concatenated K' = 3 Kp covers [z ksl, min(3 Kp, (z+1) ksl));
@@ -750,8 +765,9 @@ struct Bf16BigPlan {
 // The pre-split path pays for itself (measured on gfx950: 1.36x at 1024 x
 // 1024 x 2048, 1.9x at 4096^3, slower than the in-LDS split for thin outputs
 // such as 8192 x 128 x 1024) from 2^31 multiply-adds with both output
-// dimensions >= 1024; slices give the chip about 256 workgroups, each with
-// at least eight k steps, within 64 MiB of partials.
+// dimensions >= 1024; slices give the chip about 512 workgroups (two per
+// CU, so that one hides the other's load latency), each with at least
+// eight k steps, within 64 MiB of partials.
 static bool bf16_big_plan(int M, int N, int K, Bf16BigPlan& p) {
   if (M < 1024 || N < 1024 || K < 256 || (double)M * N * (double)K < 2147483648.0) return false;
   p.Mp = (M + XBM - 1) / XBM * XBM;
@@ -760,7 +776,7 @@ static bool bf16_big_plan(int M, int N, int K, Bf16BigPlan& p) {
   const long tiles = (long)(p.Mp / XBM) * (p.Np / XBM);
   const int ksteps = 3 * p.Kp / XBK;
   int S = 1;
-  if (tiles < 256) S = (int)std::min<long>((256 + tiles - 1) / tiles, ksteps / 8);
+  if (tiles < 512) S = (int)std::min<long>((512 + tiles - 1) / tiles, ksteps / 8);
   while (S > 1 && (long)S * M * N * 4 > (64L << 20)) --S;
   if (S < 1) S = 1;
   const int per = (ksteps + S - 1) / S;
@@ -797,19 +813,20 @@ hipError_t gemm_bf16x3_big(hipStream_t s, bool tA, bool tB, int M, int N, int K,
   float* P = p.S > 1 ? (float*)(w + p.offP) : nullptr;
   const int kind = KC_GEMM_BF16X3;
   // op(A) rows M: stored K x M when tA;  op(B)^T rows N: stored K x N unless tB
-  const double byA = 4.0 * M * K + 4.0 * p.Mp * p.Kp, byB = 4.0 * N * K + 4.0 * p.Np * p.Kp;
-  if (tA)
-    launch_timed(kind, 0.0, byA, bf16_split_kernel<true>, dim3(p.Kp / 64, p.Mp / 64), dim3(256), 0, s, A, lda, M, K,
-                 p.Kp, Ah, Al);
+  const double byS = 4.0 * (M + N) * (double)K + 4.0 * (p.Mp + p.Np) * (double)p.Kp;
+  const dim3 gs(p.Kp / 64, (p.Mp + p.Np) / 64);
+#define SPLIT2(TA_, TB_)                                                                                        \
+  launch_timed(kind, 0.0, byS, bf16_split2_kernel<TA_, TB_>, gs, dim3(256), 0, s, A, lda, M, p.Mp, B, ldb, N, K, \
+               p.Kp, Ah, Al, Bh, Bl)
+  if (tA && !tB)
+    SPLIT2(true, true);
+  else if (tA && tB)
+    SPLIT2(true, false);
+  else if (!tA && !tB)
+    SPLIT2(false, true);
   else
-    launch_timed(kind, 0.0, byA, bf16_split_kernel<false>, dim3(p.Kp / 64, p.Mp / 64), dim3(256), 0, s, A, lda, M,
-                 K, p.Kp, Ah, Al);
-  if (!tB)
-    launch_timed(kind, 0.0, byB, bf16_split_kernel<true>, dim3(p.Kp / 64, p.Np / 64), dim3(256), 0, s, B, ldb, N, K,
-                 p.Kp, Bh, Bl);
-  else
-    launch_timed(kind, 0.0, byB, bf16_split_kernel<false>, dim3(p.Kp / 64, p.Np / 64), dim3(256), 0, s, B, ldb, N,
-                 K, p.Kp, Bh, Bl);
+    SPLIT2(false, false);
+#undef SPLIT2
   const double fl = 2.0 * M * N * (double)K;
   const double by = 2.0 * 2.0 * ((double)p.Mp + p.Np) * p.Kp + 4.0 * M * N * (beta != 0.f ? 2 : 1);
   launch_timed(kind, fl, by, gemm_bf16nt_kernel, dim3(p.Np / XBM, p.Mp / XBM, p.S), dim3(256), 0, s, M, N, p.Kp,

@@ -482,6 +482,43 @@ def test_workspace_too_small_is_einval():
     assert ei.value.status == b.CTM_EINVAL
 
 
+@pytest.mark.parametrize("alt_yr,half_teal", [(False, False), (True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("D", [1, 2])
+def test_product_states_exact_energy(D, prec, alt_yr, half_teal):
+    """Degenerate input: a product state in disguise (rank-1 virtual
+    structure, D = 1 a plain product state) with chi = 6, so every projector
+    matrix has rank one and the Jacobi, the truncation and the rank-limited
+    route run on spectra that are zero past the first value.  Each bond
+    gives exactly +1/4 for S.S and -1/4 in the rotated frame (the oracle's
+    closed-form pin, every projector construction), to rounding in FP64 and
+    within the BF16x3 bounds of the other tests (5e-5 energy, 5e-4
+    gradient); the environment stays finite.  The
+    state is an eigenvector of H (every spin along the same axis: each bond
+    at the top of the S.S spectrum), a stationary point of the energy, so
+    the gradient two sweeps on vanishes to rounding (FP64) or to the split's
+    error (BF16x3)."""
+    _say("product state", D, prec, alt_yr, half_teal)
+    A_np = inp.peps_product(3 + D, 2, D)
+    obj = b.SplitCTM(torch.tensor(A_np, device=DEV), 6, 6, prec=prec, alt_yr=alt_yr, half_teal=half_teal,
+                     with_grad=True, n_sweeps=2, ckpt_every=2)
+    obj.sweep(4)
+    e, _ = obj.energy(inp.heisenberg_h())
+    e2, _ = obj.energy(inp.heisenberg_h_rotated())
+    tol = 1e-12 if prec == "fp64" else 5e-5   # BF16x3: the bound of its other energy tests (2^-17 operands)
+    assert abs(e - 0.5) < tol, e
+    assert abs(e2 + 0.5) < tol, e2
+    assert torch.isfinite(obj.env_export()).all()
+    eg, g = obj.energy_grad(inp.heisenberg_h(), 2, 2)
+    g = g.cpu().numpy()
+    obj.close()
+    assert abs(eg - 0.5) < tol and np.isfinite(g).all()
+    gn = float(np.linalg.norm(g))
+    print(f"[result] product state D={D} {prec} alt_yr={alt_yr} half_teal={half_teal}: E {e:.15f}, "
+          f"rotated {e2:.15f}, |dE/dA| {gn:.2e} (|A| {np.linalg.norm(A_np):.2f})")
+    assert gn <= (1e-12 if prec == "fp64" else 5e-4) * np.linalg.norm(A_np)
+
+
 def test_nan_input_is_enumeric():
     A_np = inp.peps_gaussian(2, 1, 1, 2, 2)
     A_np[0, 0, 0, 0, 0, 0, 0] = np.nan
