@@ -1099,8 +1099,11 @@ ctm_status ctm_workspace_size(const ctm_config* cfg, int with_grad, int n_sweeps
   return CTM_OK;
 }
 
-ctm_status ctm_init(const ctm_config* cfg, const double* A_dev, const double* bvec, void* ws, size_t ws_bytes,
-                    void* stream, ctm_ctx** out) {
+namespace {
+// aux_stream: also create the second stream and its events (contexts on the
+// static array skip them: that entry point creates no runtime objects)
+ctm_status init_ctx(const ctm_config* cfg, const double* A_dev, const double* bvec, void* ws, size_t ws_bytes,
+                    void* stream, ctm_ctx** out, bool aux_stream) {
   if (!out) return CTM_EINVAL;
   *out = nullptr;
   ctm_status st = validate(cfg);
@@ -1111,15 +1114,27 @@ ctm_status ctm_init(const ctm_config* cfg, const double* A_dev, const double* bv
   ctm_ctx* c = new (std::nothrow) ctm_ctx();
   if (!c) return CTM_ENOMEM;
   setup_ctx(c, cfg, ws, ws_bytes, (hipStream_t)stream, false);
+  if (aux_stream) {
+    Engine& E = c->E;
+    E.check(hipStreamCreateWithFlags(&E.aux, hipStreamNonBlocking));
+    for (auto& ev : E.aux_ev)
+      if (E.ok()) E.check(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
   init_persistent(c, A_dev, bvec);
   (void)need;
   st = (ctm_status)status_from_engine(c->E);
   if (st != CTM_OK) {
-    delete c;
+    ctm_destroy(c);
     return st;
   }
   *out = c;
   return CTM_OK;
+}
+}  // namespace
+
+ctm_status ctm_init(const ctm_config* cfg, const double* A_dev, const double* bvec, void* ws, size_t ws_bytes,
+                    void* stream, ctm_ctx** out) {
+  return init_ctx(cfg, A_dev, bvec, ws, ws_bytes, stream, out, true);
 }
 
 ctm_status ctm_init_static(const ctm_config* cfg, const double* A_dev, const double* bvec, void* stream,
@@ -1143,7 +1158,7 @@ ctm_status ctm_init_static(const ctm_config* cfg, const double* A_dev, const dou
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CTM_EDEVICE;
     static_ptr[dev] = p;
   }
-  st = ctm_init(cfg, A_dev, bvec, static_ptr[dev], kStaticScratchBytes, stream, out);
+  st = init_ctx(cfg, A_dev, bvec, static_ptr[dev], kStaticScratchBytes, stream, out, false);
   if (st != CTM_OK) return st;
   (*out)->static_device = dev;
   static_busy[dev] = true;
@@ -1154,6 +1169,14 @@ void ctm_destroy(ctm_ctx* c) {
   if (c && c->static_device >= 0) {
     std::lock_guard<std::mutex> lock(static_mu);
     static_busy[c->static_device] = false;
+  }
+  if (c) {
+    for (auto& ev : c->E.aux_ev)
+      if (ev) (void)hipEventDestroy(ev);
+    if (c->E.aux) {
+      (void)hipStreamSynchronize(c->E.aux);
+      (void)hipStreamDestroy(c->E.aux);
+    }
   }
   delete c;
 }

@@ -796,7 +796,16 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
       static const bool qtrace = getenv("SPLITCTM_SVD_TRACE") != nullptr;
       auto q0 = std::chrono::steady_clock::now();
       if (qtrace) check(hipStreamSynchronize(s));
-      check(qr_f64(s, (int)nb, (int)rk, 2 * (int)g, G.Xq.f64(), G.Rq.f64(), G.Qq.f64(), qwork));
+      // the Q factors are read only after the SVD: formed on the second
+      // stream (qwork stays allocated until the join below)
+      check(qr_f64_factor(s, (int)nb, (int)rk, 2 * (int)g, G.Xq.f64(), G.Rq.f64(), qwork));
+      if (aux) {
+        check(hipEventRecord(aux_ev[3], s));
+        check(hipStreamWaitEvent(aux, aux_ev[3], 0));
+        check(qr_f64_form_q(aux, (int)nb, (int)rk, 2 * (int)g, G.Qq.f64(), qwork));
+      } else {
+        check(qr_f64_form_q(s, (int)nb, (int)rk, 2 * (int)g, G.Qq.f64(), qwork));
+      }
       if (qtrace && ok()) {
         check(hipStreamSynchronize(s));
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q0).count();
@@ -814,7 +823,7 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
     auto t0 = std::chrono::steady_clock::now();
     if (trace) check(hipStreamSynchronize(s));
     check(svd_precond_f64(s, (int)n, (int)jobs[n], jM[n].f64(), jU[n].f64(), jS[n].f64(), jV[n].f64(), work,
-                          svd_max_sweeps, svd_tol, host_flags, &sweeps));
+                          svd_max_sweeps, svd_tol, host_flags, &sweeps, aux, aux ? aux_ev : nullptr));
     svd_sweeps_total += sweeps;
     svd_calls += 1;
     if (trace && ok()) {
@@ -837,7 +846,13 @@ std::vector<std::vector<Ten>> Engine::projectors_batch(const std::vector<ProjReq
   }
   // low-rank route: M = Q_L (U' S V'^T) Q_R^T stays in that factored form (the
   // QR wrote Q_L^T, Q_R^T into the persistent G.Qq); U = Q_L U', V = Q_R V' are
-  // formed only for the kept columns, below
+  // formed only for the kept columns, below.  Everything queued on the second
+  // stream (the Q factors and their QR workspaces) is joined before the
+  // transient memory is released or G.Qq is read.
+  if (aux && !dry && ok()) {
+    check(hipEventRecord(aux_ev[2], aux));
+    check(hipStreamWaitEvent(s, aux_ev[2], 0));
+  }
   ar.release(mk);
   // record the decompositions of this call for a later replay
   for (Group& G : groups) {

@@ -104,6 +104,11 @@ struct TapeRec {
 
 struct Engine {
   hipStream_t s = nullptr;
+  // second stream (default priority) for work off the critical path: the Q
+  // factors of the QRs, formed while s goes on; every use joins back into s
+  // before the call that issued it returns.  Null: everything runs on s.
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   Arena ar;
   Prec prec = Prec::F64;
   int cdt = F64;                 // dtype of contraction tensors

@@ -88,13 +88,23 @@ size_t svd_work_bytes(int n, int batch);
 // The same decomposition with QR preconditioning (columns sorted by norm,
 // A P = Q R, Jacobi SVD of R^T); falls back to svd_f64 for n > 4096.
 size_t svd_precond_work_bytes(int n, int batch);
+// qs, ev (optional: a second stream and three events): the Q factors of the
+// two preconditioning QRs are formed on qs while s goes on with the second QR
+// and the Jacobi sweeps; s waits for them before the final products.
 hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, double* U, double* S, double* V,
-                           void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out);
+                           void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out,
+                           hipStream_t qs = nullptr, hipEvent_t* ev = nullptr);
 // Householder QR of batch tall matrices X (m x k, m >= k, m <= 8192) given as
 // Xt = X^T (k x m row-major, overwritten).  R: k x k upper triangular
 // (row-major), Qt = Q^T (k x m); either may be null.
 size_t qr_work_bytes(int m, int k, int batch);
 hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R, double* Qt, void* work);
+// the two halves of qr_f64: the factorisation (R, and the reflectors and
+// block T factors kept in `work`), then Q from them (possibly on another
+// stream, ordered after the factorisation; `work` must stay untouched until
+// it has run)
+hipError_t qr_f64_factor(hipStream_t s, int m, int k, int batch, double* Xt, double* R, void* work);
+hipError_t qr_f64_form_q(hipStream_t s, int m, int k, int batch, double* Qt, void* work);
 // host_flags: host buffer of >= batch ints (convergence flags are read back
 // once per sweep; the stream is synchronised at that point).
 // V0 (optional, batch of n x n): start the iteration from G = M V0, V = V0

@@ -580,7 +580,7 @@ static int w_slices(int nt, int len, int batch) {
   return std::max(S, 1);
 }
 
-hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R, double* Qt, void* work) {
+hipError_t qr_f64_factor(hipStream_t s, int m, int k, int batch, double* Xt, double* R, void* work) {
   if (m < k || k < 1 || batch < 1) return hipErrorInvalidValue;
   if (m > 8192) return hipErrorInvalidValue;   // rows held in registers: at most 8 per thread
   QrLayout L = qr_layout(m, k, batch);
@@ -697,9 +697,24 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
     hipLaunchKernelGGL(qr_extract_r_kernel, dim3(grid_of((long)k * k), batch), dim3(256), 0, s, Xt, R, m, k, L.sX);
     e = hipGetLastError();
   }
-  if (!Qt || e != hipSuccess) return e;
+  return e;
+}
+
+// Q = H_1 ... H_k [I; 0] from the reflectors and block T factors that
+// qr_f64_factor left in `work` (which it reads and whose W buffers it uses;
+// nothing else).  It may run on another stream than the factorisation, after
+// it, while that stream goes on with work that leaves `work` alone.
+hipError_t qr_f64_form_q(hipStream_t s, int m, int k, int batch, double* Qt, void* work) {
+  if (m < k || k < 1 || batch < 1 || m > 8192) return hipErrorInvalidValue;
+  QrLayout L = qr_layout(m, k, batch);
+  char* w = (char*)work;
+  const double* Vr = (const double*)(w + L.offV);
+  const double* TB = (const double*)(w + L.offTB);
+  double* Wb = (double*)(w + L.offW);
+  double* W2b = (double*)(w + L.offW2);
+  const int nblk = (k + NBW - 1) / NBW;
   hipLaunchKernelGGL(qr_eye_kernel, dim3(grid_of((long)k * m), batch), dim3(256), 0, s, Qt, m, k, L.sX);
-  e = hipGetLastError();
+  hipError_t e = hipGetLastError();
   for (int bi = nblk - 1; bi >= 0 && e == hipSuccess; --bi) {
     const int j0 = bi * NBW, nv = std::min(k, j0 + NBW) - j0;
     const int rows = m - j0, nt = k - j0;
@@ -717,6 +732,12 @@ hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R,
     if (e == hipSuccess)
       e = gemm_f64(s, false, false, nt, rows, nv, -1.0, W2b, NBW, L.sW, Vb, m, L.sX, 1.0, Y, m, L.sX, batch);
   }
+  return e;
+}
+
+hipError_t qr_f64(hipStream_t s, int m, int k, int batch, double* Xt, double* R, double* Qt, void* work) {
+  hipError_t e = qr_f64_factor(s, m, k, batch, Xt, R, work);
+  if (e == hipSuccess && Qt) e = qr_f64_form_q(s, m, k, batch, Qt, work);
   return e;
 }
 

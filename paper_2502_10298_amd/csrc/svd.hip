@@ -815,7 +815,7 @@ __global__ void pre_transpose_kernel(const double* A_all, int n, double* B_all) 
 }
 
 struct PreLayout {
-  size_t offX, offR, offQ, offQ1, offUJ, offVJ, offN, offRk, offQW, offJW, total;
+  size_t offX, offR, offQ, offQ1, offUJ, offVJ, offN, offRk, offQW, offQW2, offJW, total;
 };
 
 static PreLayout pre_layout(int n, int batch) {
@@ -835,7 +835,8 @@ static PreLayout pre_layout(int n, int batch) {
   L.offVJ = take(nn);
   L.offN = take(sizeof(double) * (size_t)n * batch);
   L.offRk = take(sizeof(int) * (size_t)n * batch);
-  L.offQW = take(qr_work_bytes(n, n, batch));
+  L.offQW = take(qr_work_bytes(n, n, batch));    // first QR (its Q may still be formed during the second)
+  L.offQW2 = take(qr_work_bytes(n, n, batch));   // second QR
   L.offJW = take(svd_work_bytes(n, batch));
   L.total = off;
   return L;
@@ -846,7 +847,8 @@ size_t svd_precond_work_bytes(int n, int batch) {
 }
 
 hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, double* U, double* S, double* V,
-                           void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out) {
+                           void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out,
+                           hipStream_t qs, hipEvent_t* ev) {
   if (n < 1 || n > 4096) return hipErrorInvalidValue;   // the limit of svd_f64
   PreLayout L = pre_layout(n, batch);
   char* w = (char*)work;
@@ -863,12 +865,31 @@ hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, dou
   hipLaunchKernelGGL(pre_colnorm_kernel, dim3((n + 63) / 64, batch), dim3(256), 0, s, A, n, nrm);
   hipLaunchKernelGGL(pre_rank_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, (const double*)nrm, n, rk);
   hipLaunchKernelGGL(pre_gather_kernel, tiles, dim3(256), 0, s, A, (const int*)rk, n, Xt);
-  // A P = Q R (Xt holds (A P)^T)
+  // A P = Q R (Xt holds (A P)^T).  Only R feeds the second QR and the Jacobi;
+  // Q and Q1 are needed at the end, so with a second stream they are formed
+  // there while this stream runs the second QR and the sweeps (the two QRs
+  // have workspaces of their own).
+  const bool split = qs != nullptr && ev != nullptr;
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = qr_f64(s, n, n, batch, Xt, R, Qt, w + L.offQW);
+  if (e == hipSuccess) e = qr_f64_factor(s, n, n, batch, Xt, R, w + L.offQW);
+  if (e == hipSuccess && split) {
+    e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(qs, ev[0], 0);
+    if (e == hipSuccess) e = qr_f64_form_q(qs, n, n, batch, Qt, w + L.offQW);
+  } else if (e == hipSuccess) {
+    e = qr_f64_form_q(s, n, n, batch, Qt, w + L.offQW);
+  }
   // R^T = Q1 R1: the QR of the lower-triangular R^T, whose transpose is R
   // itself (R is overwritten by the reflectors; R1 lands in Xt)
-  if (e == hipSuccess) e = qr_f64(s, n, n, batch, R, Xt, Q1t, w + L.offQW);
+  if (e == hipSuccess) e = qr_f64_factor(s, n, n, batch, R, Xt, w + L.offQW2);
+  if (e == hipSuccess && split) {
+    e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(qs, ev[1], 0);
+    if (e == hipSuccess) e = qr_f64_form_q(qs, n, n, batch, Q1t, w + L.offQW2);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], qs);
+  } else if (e == hipSuccess) {
+    e = qr_f64_form_q(s, n, n, batch, Q1t, w + L.offQW2);
+  }
   // the Jacobi input is R1^T (row-major, in R)
   if (e == hipSuccess) {
     hipLaunchKernelGGL(pre_transpose_kernel, tiles, dim3(256), 0, s, (const double*)Xt, n, R);
@@ -876,6 +897,8 @@ hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, dou
   }
   if (e == hipSuccess)
     e = svd_f64(s, n, batch, R, UJ, S, VJ, w + L.offJW, max_sweeps, tol, host_flags, sweeps_out, nullptr);
+  // Q and Q1 (formed on qs) before they are read
+  if (e == hipSuccess && split) e = hipStreamWaitEvent(s, ev[2], 0);
   // R1^T = U_J S V_J^T  =>  A P = Q R1^T Q1^T... = (Q U_J) S (Q1 V_J)^T:
   // U = Q U_J, V = P Q1 V_J
   if (e == hipSuccess) e = gemm_f64(s, true, false, n, n, n, 1.0, Qt, n, nn, UJ, n, nn, 0.0, U, n, nn, batch);
