@@ -22,9 +22,15 @@
  *   - All device pointers (A, dA, workspace, env buffers) are owned by the
  *     caller; the library never allocates device memory.  The context object
  *     itself is host memory, released by ctm_destroy.
- *   - All work is enqueued on the HIP stream given to ctm_init; calls that
+ *   - All work is ordered on the HIP stream given to ctm_init; calls that
  *     return host scalars synchronise that stream.  One context per stream;
- *     calls on one context are not reentrant.
+ *     calls on one context are not reentrant.  A context made by ctm_init
+ *     also owns one internal stream of default priority (created there,
+ *     destroyed by ctm_destroy) on which the Q factors of its QR
+ *     decompositions are formed; every such piece of work is joined into the
+ *     caller's stream (stream-wait on an event) before the call that issued
+ *     it returns, so the caller sees one ordered stream.  ctm_init_static
+ *     creates no stream.
  *   - Projector SVDs, truncation, normalisation reductions and the final
  *     energy reduction are always FP64; `contract_prec` sets the precision of
  *     the tensor-network contractions.  The one-sided Jacobi SVD runs to
