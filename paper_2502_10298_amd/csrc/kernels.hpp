@@ -109,9 +109,12 @@ hipError_t qr_f64_form_q(hipStream_t s, int m, int k, int batch, double* Qt, voi
 // once per sweep; the stream is synchronised at that point).
 // V0 (optional, batch of n x n): start the iteration from G = M V0, V = V0
 // (an orthogonal matrix close to the answer, e.g. the previous sweep's V).
+// lower_tri: M is lower triangular; V is then solved for from M V = G after
+// the sweeps instead of accumulated (checked for orthogonality; the batch is
+// decomposed again with accumulated rotations where the check fails).
 hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, double* S, double* V,
                    void* work, int max_sweeps, double tol, int* host_flags, int* sweeps_out,
-                   const double* V0 = nullptr);
+                   const double* V0 = nullptr, bool lower_tri = false);
 
 // ---------------- projector formation ----------------
 // k = min(chi, #{S > cutoff * S[0]}) per batch entry -> kout (device int)

@@ -34,7 +34,8 @@ static inline int padded(int n) { return ((n + JP - 1) / JP) * JP; }
 struct SvdLayout {
   int np, nb, pairs, rounds, nchG, nchV;
   long sG, sV, sOff;
-  size_t offG, offV, offG2, offV2, offOff, offNorm, offRank, offDone, offFro, offPart, offW, offRot, offCnt, total;
+  size_t offG, offV, offG2, offV2, offOff, offNorm, offRank, offDone, offFro, offPart, offW, offRot, offCnt, offBad,
+      total;
 };
 
 static SvdLayout layout(int n, int batch) {
@@ -67,6 +68,7 @@ static SvdLayout layout(int n, int batch) {
   L.offW = take(sizeof(double) * (size_t)L.pairs * 1024 * batch);
   L.offRot = take(sizeof(int) * (size_t)L.pairs * batch);
   L.offCnt = take(sizeof(unsigned long long));
+  L.offBad = take(sizeof(int) * (size_t)batch);
   L.total = off;
   return L;
 }
@@ -568,6 +570,69 @@ __global__ void svd_scatter_kernel(const double* Gt_all, const double* Vt_all, c
   }
 }
 
+// V from the final columns when M is lower triangular: with G = M V (V the
+// product of all rotations) each row v of V^T solves v M^T = g for the row g
+// of G^T, i.e. v_c = (g_c - sum_{k<c} v_k M[c][k]) / M[c][c], forward in c.
+// Blocked: TRSM_NB columns at a time, the in-block substitution here (one
+// thread per row of V^T, right-looking so that the updates of the later
+// columns are independent of each other), the rest of the row by a rank-NB
+// GEMM update.  A triangular solve is backward stable componentwise, so the
+// result is the exact V of a matrix within n eps |M| of M, entry by entry.
+static constexpr int TRSM_NB = 64;
+
+template <bool FULL>
+__global__ __launch_bounds__(64) void trsm_rows_block_kernel(const double* __restrict__ M_all, int n, int i0,
+                                                             double* Vt_all, int ldv, long sV) {
+  const int b = blockIdx.y;
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  const double* M = M_all + (long)b * n * n + (long)i0 * n + i0;   // the diagonal block
+  double* v = Vt_all + b * sV + (long)j * ldv + i0;
+  if (FULL) {   // a whole block: the block's entries are uniform (scalar) loads
+    if (j >= n) return;
+    double x[TRSM_NB];
+#pragma unroll
+    for (int c = 0; c < TRSM_NB; ++c) x[c] = v[c];
+#pragma unroll
+    for (int c = 0; c < TRSM_NB; ++c) {
+      x[c] = x[c] / M[(long)c * n + c];
+#pragma unroll
+      for (int r = c + 1; r < TRSM_NB; ++r) x[r] -= x[c] * M[(long)r * n + c];
+    }
+#pragma unroll
+    for (int c = 0; c < TRSM_NB; ++c) v[c] = x[c];
+  } else {      // the ragged last block (nbk < TRSM_NB columns), one row per thread in LDS
+    __shared__ double xs[TRSM_NB][65];
+    const int nbk = n - i0, t = threadIdx.x;
+    const bool in = j < n;
+    for (int c = 0; c < nbk; ++c) xs[c][t] = in ? v[c] : 0.0;
+    for (int c = 0; c < nbk; ++c) {
+      const double xc = xs[c][t] / M[(long)c * n + c];
+      xs[c][t] = xc;
+      for (int r = c + 1; r < nbk; ++r) xs[r][t] -= xc * M[(long)r * n + c];
+    }
+    if (in)
+      for (int c = 0; c < nbk; ++c) v[c] = xs[c][t];
+  }
+}
+
+// bad[b] = 1 unless max |Y - I| <= tau (NaN counts as bad); Y n x n at stride sY
+__global__ void orth_check_kernel(const double* Y_all, int n, long sY, double tau, int* bad) {
+  const int b = blockIdx.x;
+  const double* Y = Y_all + b * sY;
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  int mine = 0;
+  const long tot = (long)n * n;
+  for (long e = threadIdx.x; e < tot; e += blockDim.x) {
+    const double d = Y[e] - ((e / n) == (e % n) ? 1.0 : 0.0);
+    mine |= (fabs(d) <= tau) ? 0 : 1;
+  }
+  if (mine) any = 1;   // benign race: every writer stores 1
+  __syncthreads();
+  if (threadIdx.x == 0) bad[b] = any;
+}
+
 // Y <- 1.5 I - 0.5 Y for batch n x n matrices at stride sY
 __global__ void ns_shift_kernel(double* Y_all, int n, long sY) {
   double* Y = Y_all + blockIdx.y * sY;
@@ -577,7 +642,7 @@ __global__ void ns_shift_kernel(double* Y_all, int n, long sY) {
 }
 
 hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, double* S, double* V, void* work,
-                   int max_sweeps, double tol, int* host_flags, int* sweeps_out, const double* V0) {
+                   int max_sweeps, double tol, int* host_flags, int* sweeps_out, const double* V0, bool lower_tri) {
   if (n < 1 || n > 4096) return hipErrorInvalidValue;   // the column ranks stage n norms in LDS
   if (!(tol > 0.0)) tol = 1.2e-16 * std::sqrt((double)n);   // ~ sqrt(m) eps: the rounding floor of a dot product
   SvdLayout L = layout(n, batch);
@@ -595,6 +660,10 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
   double* Wr = (double*)(w + L.offW);
   int* rot = (int*)(w + L.offRot);
   unsigned long long* cnt = (unsigned long long*)(w + L.offCnt);
+  int* bad = (int*)(w + L.offBad);
+  // V is accumulated from the rotations, or (lower-triangular M, cold start)
+  // solved for after the sweeps, which halves the rotations' memory traffic
+  const bool solveV = lower_tri && V0 == nullptr;
   // the Gram partial buffer is free until the first round: it holds the norm partials
   hipLaunchKernelGGL(svd_fro2_partial_kernel, dim3(FRO_BLOCKS, batch), dim3(256), 0, s, M, (long)n * n, part);
   hipLaunchKernelGGL(svd_fro2_final_kernel, dim3(batch), dim3(FRO_BLOCKS), 0, s, (const double*)part, fro2);
@@ -626,10 +695,12 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
                        rank);
     hipLaunchKernelGGL(svd_permute_rows_kernel, dim3(L.np, batch), dim3(256), 0, s, (const double*)Gt, Gt2,
                        (const int*)rank, n, L.np, n, L.sG);
-    hipLaunchKernelGGL(svd_permute_rows_kernel, dim3(L.np, batch), dim3(256), 0, s, (const double*)Vt, Vt2,
-                       (const int*)rank, n, L.np, L.np, L.sV);
     std::swap(Gt, Gt2);
-    std::swap(Vt, Vt2);
+    if (!solveV) {
+      hipLaunchKernelGGL(svd_permute_rows_kernel, dim3(L.np, batch), dim3(256), 0, s, (const double*)Vt, Vt2,
+                         (const int*)rank, n, L.np, L.np, L.sV);
+      std::swap(Vt, Vt2);
+    }
     // algorithmic work of one round for the batch entries still running (the
     // rotation's share is added from the device counter after the sweep)
     const double gram_fl = (double)L.pairs * running * 2.0 * JP * JP * n;
@@ -638,7 +709,8 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
       launch_timed(KC_JACOBI_GRAM, gram_fl, gram_by, jacobi_pair_kernel, dim3(L.pairs, batch), dim3(JPT), 0, s,
                    (const double*)Gt, n, L.np, r, L.sG, tol, off, L.sOff, Wr, rot, (const int*)done, inner,
                    (const double*)fro2, cnt);
-      launch_timed(KC_JACOBI_ROTATE, 0.0, 0.0, jacobi_rotate_kernel, dim3(L.pairs, nrG + nrV, batch), dim3(512), 0, s,
+      launch_timed(KC_JACOBI_ROTATE, 0.0, 0.0, jacobi_rotate_kernel, dim3(L.pairs, nrG + (solveV ? 0 : nrV), batch),
+                   dim3(512), 0, s,
                    Gt, Vt, n, L.np, r, L.sG, L.sV, (const double*)Wr, (const int*)rot, nrG, (const int*)done);
     }
     hipLaunchKernelGGL(svd_check_kernel, dim3(batch), dim3(256), 0, s, off, L.sOff, tol, done);
@@ -671,7 +743,30 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
     err = hipMemcpyAsync(&e, cnt, sizeof(e), hipMemcpyDeviceToHost, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) return err;
+    // the pair kernel counts m + np entries per rotation; the V part only
+    // when V is accumulated
+    if (solveV) e = e / (unsigned long long)(n + L.np) * (unsigned long long)n;
     tm->add(KC_JACOBI_ROTATE, 2.0 * JP * JP * (double)e, 2.0 * JP * 8.0 * (double)e);
+  }
+  if (solveV) {
+    // V^T rows = G^T rows, then the forward substitution in place
+    err = hipMemcpy2DAsync(Vt, sizeof(double) * L.np, Gt, sizeof(double) * n, sizeof(double) * n, (size_t)L.np * batch,
+                           hipMemcpyDeviceToDevice, s);
+    if (err != hipSuccess) return err;
+    for (int i0 = 0; i0 < n; i0 += TRSM_NB) {
+      const int nbk = std::min(TRSM_NB, n - i0), rest = n - i0 - nbk;
+      if (nbk == TRSM_NB)
+        hipLaunchKernelGGL(trsm_rows_block_kernel<true>, dim3((n + 63) / 64, batch), dim3(64), 0, s, M, n, i0, Vt,
+                           L.np, L.sV);
+      else
+        hipLaunchKernelGGL(trsm_rows_block_kernel<false>, dim3((n + 63) / 64, batch), dim3(64), 0, s, M, n, i0, Vt,
+                           L.np, L.sV);
+      if (rest > 0) {   // v[c] -= sum_{k in block} v[k] M[c][k] for the later columns c
+        err = gemm_f64(s, false, true, n, rest, nbk, -1.0, Vt + i0, L.np, L.sV, M + (long)(i0 + nbk) * n + i0, n,
+                       (long)n * n, 1.0, Vt + i0 + nbk, L.np, L.sV, batch);
+        if (err != hipSuccess) return err;
+      }
+    }
   }
   hipLaunchKernelGGL(svd_norms_kernel, dim3(n, batch), dim3(256), 0, s, Gt, n, L.sG, norms, L.np);
   hipLaunchKernelGGL(svd_rank_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, norms, n, L.np, rank);
@@ -698,6 +793,26 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
     for (double* X : {V, U}) {
       err = gemm_f64(s, true, false, n, n, n, 1.0, X, n, nn, X, n, nn, 0.0, Y, n, L.sV, batch);
       if (err != hipSuccess) return err;
+      if (X == V && solveV) {
+        // the solved V is orthogonal to about kappa eps, kappa the condition
+        // number of M with its rows scaled to unit length (small for the
+        // preconditioned triangle of a full-rank matrix); a numerically
+        // rank-deficient M leaves rows of rounding noise and V far from
+        // orthogonal, and the whole batch is then decomposed again with V
+        // accumulated from the rotations
+        hipLaunchKernelGGL(orth_check_kernel, dim3(batch), dim3(256), 0, s, (const double*)Y, n, L.sV, 2e-12, bad);
+        err = hipMemcpyAsync(host_flags, bad, sizeof(int) * batch, hipMemcpyDeviceToHost, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (err != hipSuccess) return err;
+        int nbad = 0;
+        for (int b = 0; b < batch; ++b) nbad += host_flags[b] ? 1 : 0;
+        if (nbad) {
+          static const bool trace = std::getenv("SPLITCTM_SVD_TRACE") != nullptr;
+          if (trace) fprintf(stderr, "[svd] n=%d: V by substitution not orthogonal in %d of %d, rotations kept\n", n,
+                             nbad, batch);
+          return svd_f64(s, n, batch, M, U, S, V, work, max_sweeps, tol, host_flags, sweeps_out, nullptr, false);
+        }
+      }
       hipLaunchKernelGGL(ns_shift_kernel, dim3((int)std::min<long>((nn + 255) / 256, 4096), batch), dim3(256), 0, s,
                          Y, n, L.sV);
       err = gemm_f64(s, false, false, n, n, n, 1.0, X, n, nn, Y, n, L.sV, 0.0, Xn, n, L.sG, batch);
@@ -896,7 +1011,7 @@ hipError_t svd_precond_f64(hipStream_t s, int n, int batch, const double* A, dou
     e = hipGetLastError();
   }
   if (e == hipSuccess)
-    e = svd_f64(s, n, batch, R, UJ, S, VJ, w + L.offJW, max_sweeps, tol, host_flags, sweeps_out, nullptr);
+    e = svd_f64(s, n, batch, R, UJ, S, VJ, w + L.offJW, max_sweeps, tol, host_flags, sweeps_out, nullptr, true);
   // Q and Q1 (formed on qs) before they are read
   if (e == hipSuccess && split) e = hipStreamWaitEvent(s, ev[2], 0);
   // R1^T = U_J S V_J^T  =>  A P = Q R1^T Q1^T... = (Q U_J) S (Q1 V_J)^T:
