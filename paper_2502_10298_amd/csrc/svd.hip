@@ -580,56 +580,68 @@ __global__ void svd_scatter_kernel(const double* Gt_all, const double* Vt_all, c
 // result is the exact V of a matrix within n eps |M| of M, entry by entry.
 static constexpr int TRSM_NB = 64;
 
+// One wavefront per 64 rows of V^T: the diagonal block of M (stored
+// transposed, so that a column of M is contiguous for 16-byte reads) and the
+// 64 x 64 tile of V^T are staged through LDS with coalesced row loads; each
+// thread then substitutes its own row in registers, reading M as wavefront-
+// uniform (broadcast) LDS values, and the tile goes back the same way.
 template <bool FULL>
 __global__ __launch_bounds__(64) void trsm_rows_block_kernel(const double* __restrict__ M_all, int n, int i0,
                                                              double* Vt_all, int ldv, long sV) {
-  const int b = blockIdx.y;
-  const int j = blockIdx.x * 64 + threadIdx.x;
+  __shared__ __attribute__((aligned(16))) double Mt[TRSM_NB][TRSM_NB + 2];   // Mt[c][r] = M[i0 + r][i0 + c]
+  __shared__ double Xs[TRSM_NB][TRSM_NB + 1];                              // Xs[row][c]
+  const int b = blockIdx.y, t = threadIdx.x, j0 = blockIdx.x * 64;
   const double* M = M_all + (long)b * n * n + (long)i0 * n + i0;   // the diagonal block
-  double* v = Vt_all + b * sV + (long)j * ldv + i0;
-  if (FULL) {   // a whole block: the block's entries are uniform (scalar) loads
-    if (j >= n) return;
-    double x[TRSM_NB];
-#pragma unroll
-    for (int c = 0; c < TRSM_NB; ++c) x[c] = v[c];
-#pragma unroll
-    for (int c = 0; c < TRSM_NB; ++c) {
-      x[c] = x[c] / M[(long)c * n + c];
-#pragma unroll
-      for (int r = c + 1; r < TRSM_NB; ++r) x[r] -= x[c] * M[(long)r * n + c];
-    }
-#pragma unroll
-    for (int c = 0; c < TRSM_NB; ++c) v[c] = x[c];
-  } else {      // the ragged last block (nbk < TRSM_NB columns), one row per thread in LDS
-    __shared__ double xs[TRSM_NB][65];
-    const int nbk = n - i0, t = threadIdx.x;
-    const bool in = j < n;
-    for (int c = 0; c < nbk; ++c) xs[c][t] = in ? v[c] : 0.0;
-    for (int c = 0; c < nbk; ++c) {
-      const double xc = xs[c][t] / M[(long)c * n + c];
-      xs[c][t] = xc;
-      for (int r = c + 1; r < nbk; ++r) xs[r][t] -= xc * M[(long)r * n + c];
-    }
-    if (in)
-      for (int c = 0; c < nbk; ++c) v[c] = xs[c][t];
+  double* Vt = Vt_all + b * sV + i0;
+  const int nbk = FULL ? TRSM_NB : n - i0;
+  for (int r = 0; r < TRSM_NB; ++r) {
+    Mt[t][r] = (r < nbk && t < nbk) ? M[(long)r * n + t] : (r == t ? 1.0 : 0.0);
+    Xs[r][t] = (j0 + r < n && t < nbk) ? Vt[(long)(j0 + r) * ldv + t] : 0.0;
   }
+  __syncthreads();
+  double x[TRSM_NB];
+#pragma unroll
+  for (int c = 0; c < TRSM_NB; ++c) x[c] = Xs[t][c];
+#pragma unroll
+  for (int c = 0; c < TRSM_NB; ++c) {
+    x[c] = x[c] / Mt[c][c];
+#pragma unroll
+    for (int r = c + 1; r < TRSM_NB; ++r) x[r] -= x[c] * Mt[c][r];
+  }
+#pragma unroll
+  for (int c = 0; c < TRSM_NB; ++c) Xs[t][c] = x[c];
+  __syncthreads();
+  for (int r = 0; r < TRSM_NB; ++r)
+    if (j0 + r < n && t < nbk) Vt[(long)(j0 + r) * ldv + t] = Xs[r][t];
 }
 
-// bad[b] = 1 unless max |Y - I| <= tau (NaN counts as bad); Y n x n at stride sY
-__global__ void orth_check_kernel(const double* Y_all, int n, long sY, double tau, int* bad) {
-  const int b = blockIdx.x;
+// Orthogonality check of Y = V^T V in two passes: part[b][k] = 1 unless
+// |Y - I| <= tau on the rows k, k + 64, ... (NaN counts as bad), then
+// bad[b] = OR of the 64 partials
+static constexpr int ORTH_PARTS = 64;
+
+__global__ __launch_bounds__(256) void orth_check_partial_kernel(const double* Y_all, int n, long sY, double tau,
+                                                                 int* part) {
+  const int b = blockIdx.y;
   const double* Y = Y_all + b * sY;
   __shared__ int any;
   if (threadIdx.x == 0) any = 0;
   __syncthreads();
   int mine = 0;
-  const long tot = (long)n * n;
-  for (long e = threadIdx.x; e < tot; e += blockDim.x) {
-    const double d = Y[e] - ((e / n) == (e % n) ? 1.0 : 0.0);
-    mine |= (fabs(d) <= tau) ? 0 : 1;
-  }
+  for (int r = blockIdx.x; r < n; r += ORTH_PARTS)
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      const double d = Y[(long)r * n + c] - (r == c ? 1.0 : 0.0);
+      mine |= (fabs(d) <= tau) ? 0 : 1;
+    }
   if (mine) any = 1;   // benign race: every writer stores 1
   __syncthreads();
+  if (threadIdx.x == 0) part[b * ORTH_PARTS + blockIdx.x] = any;
+}
+
+__global__ void orth_check_final_kernel(const int* part, int* bad) {
+  const int b = blockIdx.x;
+  int any = 0;
+  for (int k = 0; k < ORTH_PARTS; ++k) any |= part[b * ORTH_PARTS + k];
   if (threadIdx.x == 0) bad[b] = any;
 }
 
@@ -758,7 +770,7 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
       if (nbk == TRSM_NB)
         hipLaunchKernelGGL(trsm_rows_block_kernel<true>, dim3((n + 63) / 64, batch), dim3(64), 0, s, M, n, i0, Vt,
                            L.np, L.sV);
-      else
+      else   // the ragged last block: the identity pads the diagonal block
         hipLaunchKernelGGL(trsm_rows_block_kernel<false>, dim3((n + 63) / 64, batch), dim3(64), 0, s, M, n, i0, Vt,
                            L.np, L.sV);
       if (rest > 0) {   // v[c] -= sum_{k in block} v[k] M[c][k] for the later columns c
@@ -800,7 +812,10 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
         // rank-deficient M leaves rows of rounding noise and V far from
         // orthogonal, and the whole batch is then decomposed again with V
         // accumulated from the rotations
-        hipLaunchKernelGGL(orth_check_kernel, dim3(batch), dim3(256), 0, s, (const double*)Y, n, L.sV, 2e-12, bad);
+        int* opart = (int*)(w + L.offPart);   // free after the sweeps
+        hipLaunchKernelGGL(orth_check_partial_kernel, dim3(ORTH_PARTS, batch), dim3(256), 0, s, (const double*)Y, n,
+                           L.sV, 2e-12, opart);
+        hipLaunchKernelGGL(orth_check_final_kernel, dim3(batch), dim3(64), 0, s, (const int*)opart, bad);
         err = hipMemcpyAsync(host_flags, bad, sizeof(int) * batch, hipMemcpyDeviceToHost, s);
         if (err == hipSuccess) err = hipStreamSynchronize(s);
         if (err != hipSuccess) return err;

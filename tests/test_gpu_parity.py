@@ -116,6 +116,43 @@ def test_jacobi_svd(n, batch):
     assert sweeps < 60
 
 
+@pytest.mark.parametrize("n,batch", [(7, 1), (64, 2), (130, 3), (1024, 3)])
+def test_jacobi_svd_full_rank(n, batch):
+    """Full-rank inputs, plain and graded: the factor V of the preconditioned
+    triangle R1^T is solved for by substitution after the sweeps, unless the
+    check of its orthogonality sends the batch back to accumulated rotations
+    (as the rank-deficient batches of test_jacobi_svd are).  The same
+    accuracy either way: singular values to c n eps s_1, the reconstruction,
+    both factors orthogonal to working accuracy, and the leading singular
+    vectors equal to LAPACK's within eps s_1 / gap."""
+    _say("svd full rank", n, batch)
+    g = torch.Generator().manual_seed(1000 + n)
+    M = torch.randn(batch, n, n, generator=g, dtype=torch.float64)
+    if batch > 1:
+        M[1] = M[1] * torch.logspace(0, -8, n, dtype=torch.float64)[None, :]   # graded columns
+    if batch > 2:
+        M[2] = torch.logspace(0, -6, n, dtype=torch.float64)[:, None] * M[2]   # graded rows
+    U, S, V, sweeps = b.debug_svd(M.to(DEV))
+    U, S, V = U.cpu(), S.cpu(), V.cpu()
+    I = torch.eye(n, dtype=torch.float64)
+    for i in range(batch):
+        Ur, Sr, Vhr = torch.linalg.svd(M[i])
+        s1 = float(Sr[0])
+        assert float((S[i] - Sr).abs().max()) <= 4 * n * 2.2e-16 * s1
+        rec = (U[i] * S[i]) @ V[i].T
+        assert (rec - M[i]).norm() < 2e-12 * math.sqrt(n / 64 + 1) * M[i].norm()
+        assert float((V[i].T @ V[i] - I).abs().max()) <= 5e-15 * math.sqrt(n)
+        assert float((U[i].T @ U[i] - I).abs().max()) <= 1e-13 * math.sqrt(n)
+        for j in range(min(n, 6)):
+            gap = min(float(Sr[j - 1] - Sr[j]) if j > 0 else math.inf,
+                      float(Sr[j] - Sr[j + 1]) if j + 1 < n else math.inf)
+            bound = 100 * 2.2e-16 * s1 / gap + 1e-14
+            sg = 1.0 if float(V[i][:, j] @ Vhr[j]) >= 0 else -1.0
+            assert float((V[i][:, j] - sg * Vhr[j]).abs().max()) <= bound, (i, j, bound)
+            assert float((U[i][:, j] - sg * Ur[:, j]).abs().max()) <= bound, (i, j, bound)
+    assert sweeps < 60
+
+
 @pytest.mark.parametrize("m,k,batch", [(40, 17, 1), (300, 150, 3), (2048, 1024, 2), (3200, 160, 1), (64, 64, 2),
                                        (200, 130, 2), (4096, 300, 1), (1024, 1024, 3), (2100, 200, 1),
                                        (5440, 340, 1), (8192, 100, 2)])
