@@ -615,6 +615,38 @@ __global__ __launch_bounds__(64) void trsm_rows_block_kernel(const double* __res
     if (j0 + r < n && t < nbk) Vt[(long)(j0 + r) * ldv + t] = Xs[r][t];
 }
 
+// flag[b] = 1 when more than 16 diagonal entries of the triangle M_b are at
+// most 1e-13 of the largest (or any is NaN): pivots at the rounding level of
+// a numerically rank-deficient matrix.  A graded full-rank triangle has a
+// few pivots that small at most.
+__global__ __launch_bounds__(256) void svd_tiny_pivots_kernel(const double* M_all, int n, int* flag) {
+  const int b = blockIdx.x, t = threadIdx.x;
+  const double* M = M_all + (long)b * n * n;
+  __shared__ double red[256];
+  __shared__ int cnt;
+  double mx = 0.0;
+  int nan = 0;
+  for (int i = t; i < n; i += 256) {
+    const double d = fabs(M[(long)i * n + i]);
+    nan |= (d != d) ? 1 : 0;
+    mx = fmax(mx, d);
+  }
+  red[t] = mx;
+  if (t == 0) cnt = 0;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] = fmax(red[t], red[t + w]);
+    __syncthreads();
+  }
+  const double floor = 1e-13 * red[0];
+  int mine = 0;
+  for (int i = t; i < n; i += 256) mine += (fabs(M[(long)i * n + i]) <= floor) ? 1 : 0;
+  if (mine) atomicAdd(&cnt, mine);
+  if (nan) atomicAdd(&cnt, 1 << 20);
+  __syncthreads();
+  if (t == 0) flag[b] = (cnt > 16) ? 1 : 0;
+}
+
 // Orthogonality check of Y = V^T V in two passes: part[b][k] = 1 unless
 // |Y - I| <= tau on the rows k, k + 64, ... (NaN counts as bad), then
 // bad[b] = OR of the 64 partials
@@ -674,8 +706,18 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
   unsigned long long* cnt = (unsigned long long*)(w + L.offCnt);
   int* bad = (int*)(w + L.offBad);
   // V is accumulated from the rotations, or (lower-triangular M, cold start)
-  // solved for after the sweeps, which halves the rotations' memory traffic
-  const bool solveV = lower_tri && V0 == nullptr;
+  // solved for after the sweeps, which halves the rotations' memory traffic.
+  // A triangle with many pivots at the rounding level (a numerically
+  // rank-deficient M) would fail the orthogonality check of the solved V and
+  // cost a second decomposition: such a batch accumulates V from the start.
+  bool solveV = lower_tri && V0 == nullptr;
+  if (solveV) {
+    hipLaunchKernelGGL(svd_tiny_pivots_kernel, dim3(batch), dim3(256), 0, s, M, n, bad);
+    hipError_t e = hipMemcpyAsync(host_flags, bad, sizeof(int) * batch, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (int b = 0; b < batch; ++b) solveV = solveV && host_flags[b] == 0;
+  }
   // the Gram partial buffer is free until the first round: it holds the norm partials
   hipLaunchKernelGGL(svd_fro2_partial_kernel, dim3(FRO_BLOCKS, batch), dim3(256), 0, s, M, (long)n * n, part);
   hipLaunchKernelGGL(svd_fro2_final_kernel, dim3(batch), dim3(FRO_BLOCKS), 0, s, (const double*)part, fro2);
