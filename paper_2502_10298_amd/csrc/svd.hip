@@ -615,10 +615,13 @@ __global__ __launch_bounds__(64) void trsm_rows_block_kernel(const double* __res
     if (j0 + r < n && t < nbk) Vt[(long)(j0 + r) * ldv + t] = Xs[r][t];
 }
 
-// flag[b] = 1 when more than 16 diagonal entries of the triangle M_b are at
-// most 1e-13 of the largest (or any is NaN): pivots at the rounding level of
-// a numerically rank-deficient matrix.  A graded full-rank triangle has a
-// few pivots that small at most.
+// flag[b] = 1 when more than max(16, n / 4) diagonal entries of the triangle
+// M_b are at most 1e-13 of the largest (or any is NaN): many pivots at the
+// rounding level of a numerically rank-deficient matrix.  The count is a
+// predictor only (triangles with more such pivots often pass the check of
+// the solved V, and some with none fail it); the bound balances a second
+// decomposition against the rotations of V on the projector matrices of the
+// 2x2 D = 8 and the chi = 170 scaling workloads.
 __global__ __launch_bounds__(256) void svd_tiny_pivots_kernel(const double* M_all, int n, int* flag) {
   const int b = blockIdx.x, t = threadIdx.x;
   const double* M = M_all + (long)b * n * n;
@@ -644,7 +647,7 @@ __global__ __launch_bounds__(256) void svd_tiny_pivots_kernel(const double* M_al
   if (mine) atomicAdd(&cnt, mine);
   if (nan) atomicAdd(&cnt, 1 << 20);
   __syncthreads();
-  if (t == 0) flag[b] = (cnt > 16) ? 1 : 0;
+  if (t == 0) flag[b] = (cnt > max(16, n / 4)) ? 1 : 0;
 }
 
 // Orthogonality check of Y = V^T V in two passes: part[b][k] = 1 unless
