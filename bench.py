@@ -71,7 +71,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grad-sweeps", type=int, default=4)
     ap.add_argument("--ckpt", type=int, default=4)
-    ap.add_argument("--pre-sweeps", type=int, default=8, help="untimed sweeps that converge the start environment")
+    ap.add_argument("--pre-sweeps", type=int, default=8,
+                    help="untimed sweeps from the identity boundary that build the start environment (its corner-spectrum change is reported as start_env_delta)")
     ap.add_argument("--fwd-sweeps", type=int, default=4, help="timed forward-only sweeps for sweeps/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -335,9 +336,11 @@ def main():
         return o
 
     obj = context(prec)
-    # untimed: converge the start environment (an optimisation step starts from
-    # the previous step's environment); every timed step and every leg starts
-    # from this same environment
+    # untimed: the start environment, grown from the identity boundary (an
+    # optimisation step starts from the previous step's environment, not from
+    # the boundary); every timed step and every leg starts from this same
+    # environment.  It is not converged (the change of the corner spectra over
+    # its last sweep is reported)
     st, n, delta = obj.sweep(args.pre_sweeps, 0.0)
     flat0 = obj.env_export()
     obj.env_import(flat0)
