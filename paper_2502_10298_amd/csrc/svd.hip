@@ -2,7 +2,8 @@
 // M = U S V^T of the split-CTMRG projector recipe.
 //
 // The columns of G = M are orthogonalised by orthogonal rotations G <- G W,
-// accumulated in V <- V W; at convergence G = U S.  Columns are grouped in
+// accumulated in V <- V W (or, for a lower-triangular M, V is solved for from
+// M V = G once after the sweeps); at convergence G = U S.  Columns are grouped in
 // blocks of 16; a round-robin tournament pairs the blocks so that every
 // round updates disjoint column sets in parallel.  For each block pair the
 // 32 x 32 Gram matrix of its columns is formed from the actual columns,
@@ -833,8 +834,9 @@ hipError_t svd_f64(hipStream_t s, int n, int batch, const double* M, double* U, 
     hipLaunchKernelGGL(svd_scatter_kernel, dim3(g, batch), dim3(256), 0, s, Gt, Vt, norms, rank, n, L.np, L.sG, L.sV,
                        U, S, V);
   }
-  // V is the product of every rotation of every sweep: each is orthogonal to
-  // rounding, but their product drifts (~1e-13 after ten sweeps at n ~ 1000);
+  // An accumulated V is the product of every rotation of every sweep: each is
+  // orthogonal to rounding, but their product drifts (~1e-13 after ten sweeps
+  // at n ~ 1000); a solved V is orthogonal to ~kappa eps (checked below);
   // U = G / |G| is orthogonal to the stopping tolerance.  The reverse pass of
   // a truncated SVD with a strongly graded spectrum (s_k / s_1 down to 1e-8)
   // turns an orthogonality defect d into a gradient error of about
