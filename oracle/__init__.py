@@ -22,12 +22,15 @@ conventional_ctmrg
     projectors, sharing no code with split_ctmrg.
 
 Parity status: the teal and red half networks are a reading of the paper
-(their figures are missing from the source); they are pinned end to end only
+(their figures are missing from the source).  They are pinned end to end
 (Ising closed forms, product states, agreement with the conventional CTMRG,
-2x2 cell = 1x1 cell for a translation-invariant state), not network by
-network: "parity unpinned" at the level of the individual teal / red
-networks.  The same holds for the teal half networks of App. B (their figure
-has no body either): pinned end to end by product states, Onsager and
-convergence to the conventional CTMRG.  The alternative yellow / red networks
-follow complete figures and are pinned the same way, plus exact half-steps.
+2x2 cell = 1x1 cell for a translation-invariant state) and network by
+network: with no truncation the first projector pairs are resolutions of the
+identity, so each teal and red pair of half networks contracts to the plain
+norm of the patch it cuts, computed independently from the untouched
+environment and site tensors (tests/test_oracle_networks.py; the teal half
+networks of App. B likewise, against the column patch closed on itself).
+The alternative yellow / red networks of App. B follow complete figures and
+are pinned end to end plus exact half-steps (their mirrored yellow pair is
+of lower rank and never the identity).
 """

@@ -19,10 +19,12 @@ Readings of the paper (it is silent or its figures are missing):
     the other legs).  A 1-column patch closed by the column's own right
     environment leaves chi_E stuck at 1 from the identity boundary, since M
     then spans that environment's single bond (the teal half projectors below
-    leave those legs open instead).  No figure of the paper fixes these networks, so they are pinned
-    end to end only: Ising free energy and magnetisation against Onsager,
+    leave those legs open instead).  No figure of the paper fixes these networks; they are pinned
+    end to end (Ising free energy and magnetisation against Onsager,
     product states, agreement with the conventional double-layer CTMRG as
-    chi grows, a translation-invariant 2x2 cell equal to the 1x1 cell.
+    chi grows, a translation-invariant 2x2 cell equal to the 1x1 cell) and
+    one by one: without truncation each pair contracts to the norm of the
+    patch it cuts.
   * singular values below cutoff * s_1 are dropped (cutoff 1e-12);
   * canonical sign: the entry of largest magnitude of every column of P_T is
     made positive (lowest index on ties), flipping the matching column of P_B;
@@ -297,6 +299,54 @@ def right_intermediate(env, A, Lx, y, Gr, Yr, alt_yr=False):
     return C2t, T2kt, T2bt, C3t
 
 
+def teal_red_networks(env, A, Lx, y, yn, x, left, right, alt_yr=False, half_teal=False):
+    """Half networks of the teal cut (x|x+1) and of the red cut of row x,
+    between column y (its ket layer absorbed into the left intermediate
+    environment `left` = (C1t, T4kt, T4bt, C4t)) and column yn (its bra layer
+    absorbed into the right intermediate environment `right` = (C2t, T2kt,
+    T2bt, C3t)).  Returns (rho^T_teal, rho^B_teal, rho^T_red, rho^B_red,
+    number of truncated legs of the red networks)."""
+    C1t, T4kt, T4bt, C4t = left
+    C2t, T2kt, T2bt, C3t = right
+    xp = (x + 1) % Lx
+    m, mp = env[(x, y)], env[(xp, y)]          # middle: bra part of column y
+    n, np_ = env[(x, yn)], env[(xp, yn)]       # middle: ket part of column y+1
+    b, bp = A[(x, y)], A[(xp, y)]
+    k, kp = A[(x, yn)], A[(xp, yn)]
+    if alt_yr:
+        rT = ncon("ae,efh,hci,ij,aSY,YwGP,PfwBk,QcSKr,jrZQ,ZkF->GBKF",
+                  C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
+                  T2kt[x], T2bt[x])
+        rB = ncon("GSY,YwvP,vq,hoq,iXh,ni,PBwok,QKSXr,FrZQ,Zkn->GBKF",
+                  T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
+                  T2kt[xp], T2bt[xp])
+        sT = ncon("ae,eWh,hci,ij,aSY,QcSKr,jrJQ->YWKJ",
+                  C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
+        sB = ncon("YwvP,vq,hoq,iKh,ni,PWwok,Jkn->YWKJ",
+                  T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
+        n_red = 2
+    else:
+        rT = ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
+                  C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
+                  T2kt[x], T2bt[x])
+        rB = ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
+                  T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
+                  T2kt[xp], T2bt[xp])
+        sT = ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
+                  C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
+        sB = ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
+                  T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
+        n_red = 3
+    if half_teal:
+        if alt_yr:
+            rT = ncon("ae,efh,aSY,YwGP,PfwBk->GBhSk", C1t[x], m["T1b"], T4kt[x], T4bt[x], b)
+            rB = ncon("GSY,YwvP,vq,hoq,PBwok->GBhSk", T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], bp)
+        else:
+            rT = ncon("ae,efh,aSYP,YwG,PfwBk->GBhSk", C1t[x], m["T1b"], T4kt[x], T4bt[x], b)
+            rB = ncon("GSYP,Ywv,vq,hoq,PBwok->GBhSk", T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], bp)
+    return rT, rB, sT, sB, n_red
+
+
 def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-12, alt_yr=False,
                       half_teal=False):
     """Steps 1-3 of the left move of column y: green / yellow projectors,
@@ -314,42 +364,8 @@ def column_projectors(env, A, Lx, Ly, y, chi_E, chi_I, cutoff=1e-12, adj_eps=1e-
     C2t, T2kt, T2bt, C3t = right_intermediate(env, A, Lx, yn, Gr, Yr, alt_yr)
     TH, R = {}, {}
     for x in range(Lx):
-        xp = (x + 1) % Lx
-        m, mp = env[(x, y)], env[(xp, y)]          # middle: bra part of column y
-        n, np_ = env[(x, yn)], env[(xp, yn)]       # middle: ket part of column y+1
-        b, bp = A[(x, y)], A[(xp, y)]
-        k, kp = A[(x, yn)], A[(xp, yn)]
-        if alt_yr:
-            rT = ncon("ae,efh,hci,ij,aSY,YwGP,PfwBk,QcSKr,jrZQ,ZkF->GBKF",
-                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
-                      T2kt[x], T2bt[x])
-            rB = ncon("GSY,YwvP,vq,hoq,iXh,ni,PBwok,QKSXr,FrZQ,Zkn->GBKF",
-                      T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
-                      T2kt[xp], T2bt[xp])
-            sT = ncon("ae,eWh,hci,ij,aSY,QcSKr,jrJQ->YWKJ",
-                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
-            sB = ncon("YwvP,vq,hoq,iKh,ni,PWwok,Jkn->YWKJ",
-                      T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
-            n_red = 2
-        else:
-            rT = ncon("ae,efh,hci,ij,aSYP,YwG,PfwBk,QcSKr,jrZ,ZkFQ->GBKF",
-                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], T4bt[x], b, k,
-                      T2kt[x], T2bt[x])
-            rB = ncon("GSYP,Ywv,vq,hoq,iXh,ni,PBwok,QKSXr,FrZ,ZknQ->GBKF",
-                      T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], np_["T3k"], C3t[xp], bp, kp,
-                      T2kt[xp], T2bt[xp])
-            sT = ncon("ae,eWh,hci,ij,aSYP,QcSKr,jrJ->YPWKQJ",
-                      C1t[x], m["T1b"], n["T1k"], C2t[x], T4kt[x], k, T2kt[x])
-            sB = ncon("Ywv,vq,hoq,iKh,ni,PWwok,JknQ->YPWKQJ",
-                      T4bt[x], C4t[x], m["T3b"], n["T3k"], C3t[x], b, T2bt[x])
-            n_red = 3
-        if half_teal:
-            if alt_yr:
-                rT = ncon("ae,efh,aSY,YwGP,PfwBk->GBhSk", C1t[x], m["T1b"], T4kt[x], T4bt[x], b)
-                rB = ncon("GSY,YwvP,vq,hoq,PBwok->GBhSk", T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], bp)
-            else:
-                rT = ncon("ae,efh,aSYP,YwG,PfwBk->GBhSk", C1t[x], m["T1b"], T4kt[x], T4bt[x], b)
-                rB = ncon("GSYP,Ywv,vq,hoq,PBwok->GBhSk", T4kt[xp], T4bt[xp], C4t[xp], mp["T3b"], bp)
+        rT, rB, sT, sB, n_red = teal_red_networks(env, A, Lx, y, yn, x, (C1t, T4kt, T4bt, C4t),
+                                                  (C2t, T2kt, T2bt, C3t), alt_yr, half_teal)
         TH[x] = projectors(rT, rB, 2, chi_E, cutoff, adj_eps)
         R[x] = projectors(sT, sB, n_red, chi_I, cutoff, adj_eps)
     return G, Y, TH, R, (C1t, T4kt, T4bt, C4t)
